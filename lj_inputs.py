@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs for the short-range Lennard-Jones MD hot path.
+
+This module only draws inputs: an fcc lattice at a given reduced density,
+uniform positional jitter, Maxwell velocities, a 50/50 two-type assignment and
+per-type-pair (epsilon, sigma) draws.  It holds none of the method's
+arithmetic (no distances, forces, neighbor tests or integration) and imports
+neither the oracle nor the HIP package; both of those consume what it returns.
+
+The state point is the classic dense LJ liquid used for the LJ benchmark kernel
+the paper names (CabanaMD proxy-app section): fcc at rho* = 0.8442,
+T* = 1.44, cutoff 2.5 sigma, skin 0.3 sigma.  All quantities are in LJ reduced
+units (mass 1, k_B 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+SEED_BASE = 20210919
+
+# fcc conventional-cell basis, in units of the lattice constant
+_FCC_BASIS = np.array(
+    [[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One benchmark/parity configuration (sizes follow the paper's dense-LJ state point)."""
+    name: str
+    index: int              # seeds derive from SEED_BASE + index
+    cells: int              # fcc unit cells per box edge
+    density: float = 0.8442
+    temperature: float = 1.44
+    rc: float = 2.5
+    skin: float = 0.3
+    dt: float = 0.005
+    steps: int = 0
+    rebuild_every: int = 20
+    ntypes: int = 1
+    jitter: float = 0.05
+    checkpoint_every: int = 0
+
+    @property
+    def natoms(self) -> int:
+        return 4 * self.cells ** 3
+
+    @property
+    def rlist(self) -> float:
+        return self.rc + self.skin
+
+    @property
+    def lattice_constant(self) -> float:
+        return (4.0 / self.density) ** (1.0 / 3.0)
+
+    @property
+    def box(self) -> np.ndarray:
+        return np.full(3, self.cells * self.lattice_constant)
+
+
+WORKLOADS = {
+    "lj256": Workload("lj256", 0, cells=4, steps=100),
+    "lj32k": Workload("lj32k", 1, cells=20, steps=1000),
+    "lj500k": Workload("lj500k", 2, cells=50, steps=1000),
+    "lj32k_fm": Workload("lj32k_fm", 3, cells=20, ntypes=2),
+    "lj256k_traj": Workload("lj256k_traj", 4, cells=40, steps=20, ntypes=2,
+                            checkpoint_every=5),
+}
+
+
+def rng(workload: Workload, stream: int) -> np.random.Generator:
+    """PCG64 stream: 0 jitter, 1 velocities, 2 types, 3 parameters, 4 perturbation."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + workload.index + stream))
+
+
+def fcc_lattice(cells: int, a: float) -> np.ndarray:
+    """Perfect fcc positions, loop order ix, iy, iz, basis atom; shape [4*cells^3, 3]."""
+    idx = np.arange(cells)
+    ix, iy, iz = np.meshgrid(idx, idx, idx, indexing="ij")
+    origins = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    pos = (origins[:, None, :] + _FCC_BASIS[None, :, :]).reshape(-1, 3)
+    return pos * a
+
+
+def _into_box(x: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """Fold freshly drawn positions into [0, L) (input preparation only)."""
+    x = np.where(x < 0.0, x + L, x)
+    x = np.where(x >= L, x - L, x)
+    return np.where(x >= L, x - L, x)
+
+
+def positions(workload: Workload, jitter: float | None = None) -> np.ndarray:
+    """Jittered fcc positions in [0, L)^3, FP64 [N, 3]."""
+    j = workload.jitter if jitter is None else jitter
+    x = fcc_lattice(workload.cells, workload.lattice_constant)
+    if j > 0.0:
+        x = x + rng(workload, 0).uniform(-j, j, size=x.shape)
+    return _into_box(x, workload.box)
+
+
+def velocities(workload: Workload, n: int | None = None) -> np.ndarray:
+    """Maxwell velocities at T (m = 1), zero total momentum, kinetic T exact with 3N-3 dof."""
+    n = workload.natoms if n is None else n
+    v = rng(workload, 1).normal(0.0, np.sqrt(workload.temperature), size=(n, 3))
+    v -= v.mean(axis=0)
+    t_now = (v * v).sum() / (3 * n - 3)
+    return v * np.sqrt(workload.temperature / t_now)
+
+
+def types(workload: Workload, n: int | None = None) -> np.ndarray:
+    """int32 types: exactly floor(N/T) of each type via a seeded permutation (0 for one type)."""
+    n = workload.natoms if n is None else n
+    t = np.zeros(n, dtype=np.int32)
+    if workload.ntypes > 1:
+        perm = rng(workload, 2).permutation(n)
+        per = n // workload.ntypes
+        for k in range(1, workload.ntypes):
+            t[perm[k * per:(k + 1) * per]] = k
+    return t
+
+
+def npacked(ntypes: int) -> int:
+    return ntypes * (ntypes + 1) // 2
+
+
+def params(workload: Workload) -> tuple[np.ndarray, np.ndarray]:
+    """Packed upper-triangle (eps, sigma), entry order (0,0),(0,1),...,(0,T-1),(1,1),...
+
+    One type: eps = sigma = 1.  Several types: eps ~ U[0.8, 1.2], sigma ~ U[0.9, 1.1].
+    """
+    p = npacked(workload.ntypes)
+    if workload.ntypes == 1:
+        return np.ones(1), np.ones(1)
+    g = rng(workload, 3)
+    eps = g.uniform(0.8, 1.2, size=p)
+    sigma = g.uniform(0.9, 1.1, size=p)
+    return eps, sigma
+
+
+def perturbed_params(workload: Workload, rel: float = 0.05) -> tuple[np.ndarray, np.ndarray]:
+    """Target parameters: each packed entry scaled by (1 + delta), delta ~ U[-rel, rel]."""
+    eps, sigma = params(workload)
+    g = rng(workload, 4)
+    return (eps * (1.0 + g.uniform(-rel, rel, size=eps.shape)),
+            sigma * (1.0 + g.uniform(-rel, rel, size=sigma.shape)))
+
+
+def make_system(workload: Workload):
+    """Everything one run needs: x, v, types, ids, packed eps/sigma, box."""
+    x = positions(workload)
+    n = x.shape[0]
+    eps, sigma = params(workload)
+    return dict(x=x, v=velocities(workload, n), types=types(workload, n),
+                ids=np.arange(n, dtype=np.int64), eps=eps, sigma=sigma,
+                box=workload.box.copy())
+
+
+def random_gas(n: int, L, seed: int) -> np.ndarray:
+    """Uniform random positions in [0, L)^3 (ragged/edge-case tests)."""
+    L = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    g = np.random.Generator(np.random.PCG64(seed))
+    return _into_box(g.uniform(0.0, 1.0, size=(n, 3)) * L, L)

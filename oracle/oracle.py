@@ -1,0 +1,308 @@
+"""Python face of the CPU FP64 oracle (test infrastructure only).
+
+The arithmetic lives in oracle.c (O(N^2) all pairs, minimum image, FP64);
+this module marshals NumPy arrays and writes out, in plain Python, the few
+steps that are pure bookkeeping: the counting-sort order as a lexicographic
+sort, the half list as the unordered pairs of the full relation, the
+velocity-Verlet loop with its fixed rebuild cadence, and the discrete adjoint
+of that loop.  See oracle.c for the definitions and their citations.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+_lock = threading.Lock()
+
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_VP = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+
+
+def lib():
+    """Load liborc.so, building it from oracle.c if it is missing or stale."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            src = os.path.join(_HERE, "oracle.c")
+            if (not os.path.exists(_LIB_PATH)
+                    or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src)):
+                from . import build as _b
+                _b.build()
+            L = ctypes.CDLL(_LIB_PATH)
+            L.orc_grid.argtypes = [_D, _dbl, _I32]
+            L.orc_cell_index.argtypes = [_i64, _D, _D, _I32, _I64]
+            L.orc_neighbor_count.argtypes = [_i64, _D, _D, _dbl, _i64, _VP, _I32]
+            L.orc_neighbor_count.restype = _i64
+            L.orc_neighbor_fill.argtypes = [_i64, _D, _D, _dbl, _i64, _VP, _I64, _I32]
+            L.orc_forces.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl, _i64,
+                                     _VP, _D, _D, _D, _VP]
+            L.orc_forces_list.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl,
+                                          _I64, _I32, _D, _D, _D]
+            L.orc_force_vjp.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl, _VP,
+                                        _VP, _D, _D, _D, _D]
+            L.orc_kick_drift.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _VP]
+            L.orc_kick.argtypes = [_i64, _D, _D, _dbl, _dbl]
+            _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _box(L):
+    return _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def ntypes_of(eps) -> int:
+    p = int(np.asarray(eps).size)
+    t = int(round((np.sqrt(8 * p + 1) - 1) / 2))
+    assert t * (t + 1) // 2 == p, "packed parameter length must be T(T+1)/2"
+    return t
+
+
+# ------------------------------------------------------------------ binning --
+
+def grid(L, rlist) -> np.ndarray:
+    nc = np.zeros(3, dtype=np.int32)
+    lib().orc_grid(_box(L), float(rlist), nc)
+    return nc
+
+
+def cell_index(x, L, nc) -> np.ndarray:
+    x = _f64(x)
+    out = np.zeros(x.shape[0], dtype=np.int64)
+    lib().orc_cell_index(x.shape[0], x, _box(L), np.ascontiguousarray(nc, dtype=np.int32), out)
+    return out
+
+
+def bin_order(x, ids, L, rlist):
+    """Counting sort by cell, ascending id inside a cell: a stable order on (cell, id).
+
+    Returns (perm, cell_start, nc): sorted position k holds input atom perm[k];
+    cell_start[c] is the first sorted position of cell c (length ncells + 1).
+    """
+    nc = grid(L, rlist)
+    cell = cell_index(x, L, nc)
+    perm = np.lexsort((np.asarray(ids), cell))
+    ncell = int(np.prod(nc.astype(np.int64)))
+    counts = np.bincount(cell, minlength=ncell)
+    cell_start = np.zeros(ncell + 1, dtype=np.int64)
+    np.cumsum(counts, out=cell_start[1:])
+    return perm, cell_start, nc
+
+
+# ---------------------------------------------------------------- neighbors --
+
+def neighbor_lists(x, L, rlist, sel=None):
+    """Full Verlet list by brute force: CSR (offsets, nbr), each row j-ascending.
+
+    Rows are all atoms, or the atoms in sel (then offsets has len(sel)+1 entries).
+    """
+    x = _f64(x)
+    n = x.shape[0]
+    sel_a = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    rows = n if sel_a is None else sel_a.size
+    counts = np.zeros(rows, dtype=np.int32)
+    lib().orc_neighbor_count(n, x, _box(L), float(rlist), rows, _ptr(sel_a), counts)
+    offsets = np.zeros(rows + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    nbr = np.zeros(max(int(offsets[-1]), 1), dtype=np.int32)
+    lib().orc_neighbor_fill(n, x, _box(L), float(rlist), rows, _ptr(sel_a), offsets, nbr)
+    return offsets, nbr[:offsets[-1]]
+
+
+def half_pairs(offsets, nbr, rows=None) -> np.ndarray:
+    """Unordered pairs {min, max} of a full relation, as a sorted [P, 2] int64 array."""
+    n = offsets.size - 1
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    i = np.repeat(rows, np.diff(offsets))
+    j = nbr.astype(np.int64)
+    a = np.minimum(i, j)
+    b = np.maximum(i, j)
+    pairs = np.unique(np.stack([a, b], axis=1), axis=0)
+    return pairs
+
+
+# ------------------------------------------------------------------- forces --
+
+def forces(x, L, rc, eps=(1.0,), sigma=(1.0,), types=None, sel=None):
+    """All-pairs F, e (per row), W[6] and unordered pair counts within rc per type pair."""
+    x = _f64(x)
+    n = x.shape[0]
+    eps = _f64(np.atleast_1d(eps))
+    sigma = _f64(np.atleast_1d(sigma))
+    T = ntypes_of(eps)
+    t = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    sel_a = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    rows = n if sel_a is None else sel_a.size
+    F = np.zeros((rows, 3))
+    e = np.zeros(rows)
+    W = np.zeros(6)
+    npairs = np.zeros(eps.size, dtype=np.int64)
+    lib().orc_forces(n, x, _ptr(t), T, eps, sigma, _box(L), float(rc), rows, _ptr(sel_a),
+                     F, e, W, _ptr(npairs))
+    return F, e, W, npairs
+
+
+def forces_list(x, L, rc, offsets, nbr, eps=(1.0,), sigma=(1.0,), types=None):
+    x = _f64(x)
+    n = x.shape[0]
+    eps = _f64(np.atleast_1d(eps))
+    sigma = _f64(np.atleast_1d(sigma))
+    t = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    F = np.zeros((n, 3))
+    e = np.zeros(n)
+    W = np.zeros(6)
+    lib().orc_forces_list(n, x, _ptr(t), ntypes_of(eps), eps, sigma, _box(L), float(rc),
+                          np.ascontiguousarray(offsets, dtype=np.int64),
+                          np.ascontiguousarray(nbr, dtype=np.int32), F, e, W)
+    return F, e, W
+
+
+def force_vjp(x, L, rc, g, eps=(1.0,), sigma=(1.0,), types=None, offsets=None, nbr=None):
+    """(gx, geps, gsigma) = g^T dF/d(x, eps, sigma) with the pair set held fixed."""
+    x = _f64(x)
+    n = x.shape[0]
+    eps = _f64(np.atleast_1d(eps))
+    sigma = _f64(np.atleast_1d(sigma))
+    t = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    off = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64)
+    nb = None if nbr is None else np.ascontiguousarray(nbr, dtype=np.int32)
+    gx = np.zeros((n, 3))
+    ge = np.zeros(eps.size)
+    gs = np.zeros(eps.size)
+    lib().orc_force_vjp(n, x, _ptr(t), ntypes_of(eps), eps, sigma, _box(L), float(rc),
+                        _ptr(off), _ptr(nb), _f64(g), gx, ge, gs)
+    return gx, ge, gs
+
+
+def pair_energy(r, eps=1.0, sigma=1.0):
+    """12-6 pair energy for scalar r (no cutoff), via the oracle's two-atom force call."""
+    L = np.full(3, 1e3)
+    x = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]]) + 10.0
+    F, e, _, _ = forces(x, L, rc=1e2, eps=[eps], sigma=[sigma])
+    return 2.0 * e[0], F
+
+
+# --------------------------------------------------------------- integrator --
+
+def kick_drift(x, v, F, dt, L, mass=1.0, img=None):
+    """In place: v += dt/2 F/m; x += dt v; wrap into [0, L)."""
+    lib().orc_kick_drift(x.shape[0], x, v, _f64(F), float(dt), float(mass), _box(L),
+                         _ptr(img))
+
+
+def kick(v, F, dt, mass=1.0):
+    lib().orc_kick(v.shape[0], v, _f64(F), float(dt), float(mass))
+
+
+def run_nve(x, v, L, rc, rlist, dt, steps, rebuild_every=20, eps=(1.0,), sigma=(1.0,),
+            types=None, mode="verlet", record=None):
+    """Velocity-Verlet NVE run.
+
+    mode "verlet": the oracle's own brute-force list, rebuilt every
+    rebuild_every steps from step 0 with no displacement check; "allpairs":
+    every force call over all pairs.  Returns (x, v, F, thermo) where thermo is
+    a list of (step, PE, KE) and `record` (a set of steps) selects snapshots
+    returned in thermo-side dict `snaps`.
+    """
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    n = x.shape[0]
+    img = np.zeros((n, 3), dtype=np.int32)
+    lst = None
+
+    def force(step):
+        nonlocal lst
+        if mode == "allpairs":
+            F, e, W, _ = forces(x, L, rc, eps, sigma, types)
+            return F, e
+        if step % rebuild_every == 0 or lst is None:
+            lst = neighbor_lists(x, L, rlist)
+        F, e, W = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+        return F, e
+
+    F, e = force(0)
+    thermo = [(0, e.sum(), 0.5 * (v * v).sum())]
+    snaps = {}
+    if record and 0 in record:
+        snaps[0] = (x.copy(), v.copy(), F.copy())
+    for step in range(1, steps + 1):
+        kick_drift(x, v, F, dt, L, img=img)
+        F, e = force(step)
+        kick(v, F, dt)
+        thermo.append((step, e.sum(), 0.5 * (v * v).sum()))
+        if record and step in record:
+            snaps[step] = (x.copy(), v.copy(), F.copy())
+    return x, v, F, thermo, snaps, img
+
+
+# ------------------------------------------------------- trajectory adjoint --
+
+def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None):
+    """Forward velocity Verlet with one list built at step 0 (steps <= rebuild cadence).
+
+    Returns (xs, v_T, unwrapped x_T, lst): xs[k] is the wrapped position at step k.
+    """
+    x = _f64(x0).copy()
+    v = _f64(v0).copy()
+    img = np.zeros(x.shape, dtype=np.int32)
+    lst = neighbor_lists(x, L, rlist)
+    F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+    xs = [x.copy()]
+    for _ in range(steps):
+        kick_drift(x, v, F, dt, L, img=img)
+        F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+        kick(v, F, dt)
+        xs.append(x.copy())
+    return xs, v, x + img * _box(L), lst
+
+
+def trajectory_adjoint(xs, L, rc, dt, eps, sigma, xbar_T, vbar_T, types=None, lst=None):
+    """Discrete adjoint of the velocity-Verlet trajectory, newest step first.
+
+    Step n maps (x_n, v_n) to (x_{n+1}, v_{n+1}) through h = v_n + dt/2 F(x_n),
+    x_{n+1} = x_n + dt h, v_{n+1} = h + dt/2 F(x_{n+1}).  Its reverse, with
+    J^T a the force VJP at the stated positions:
+        xbar_{n+1} += J^T(x_{n+1}) (dt/2 vbar_{n+1});  hbar = vbar_{n+1} + dt xbar_{n+1}
+        xbar_n = xbar_{n+1} + J^T(x_n) (dt/2 hbar);    vbar_n = hbar
+    Parameter cotangents collect the same VJP calls.  Returns
+    (xbar_0, vbar_0, geps, gsigma).
+    """
+    T = len(xs) - 1
+    xbar = _f64(xbar_T).copy()
+    vbar = _f64(vbar_T).copy()
+    ge = np.zeros(np.asarray(eps).size)
+    gs = np.zeros(np.asarray(eps).size)
+    off, nb = (None, None) if lst is None else lst
+
+    def vjp(x, a):
+        return force_vjp(x, L, rc, a, eps, sigma, types, off, nb)
+
+    for n in range(T - 1, -1, -1):
+        gx, e1, s1 = vjp(xs[n + 1], 0.5 * dt * vbar)
+        xbar += gx
+        ge += e1
+        gs += s1
+        hbar = vbar + dt * xbar
+        gx, e2, s2 = vjp(xs[n], 0.5 * dt * hbar)
+        xbar = xbar + gx
+        ge += e2
+        gs += s2
+        vbar = hbar
+    return xbar, vbar, ge, gs
