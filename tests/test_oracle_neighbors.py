@@ -90,3 +90,21 @@ def test_bin_order(orc):
     for c in range(int(np.prod(nc))):
         assert np.all(cs[cell_start[c]:cell_start[c + 1]] == c)
     assert cell_start[-1] == 700
+
+
+def test_bin_upper_edge(orc):
+    # box edges where x just below L gives x/h == nc after rounding: such atoms
+    # belong to the last cell, never to cell 0
+    L = np.array([15.980117845432297, 26.507607108814266, 27.54778587512588])
+    x = li.random_gas(50, L, seed=2)
+    edge = np.nextafter(L, 0.0)
+    x[:3] = [[edge[0], 1.0, 1.0], [1.0, edge[1], 1.0], [1.0, 1.0, edge[2]]]
+    x[3] = [0.0, 0.0, 0.0]
+    nc = orc.grid(L, 2.8)
+    assert np.any(np.floor(edge / (L / nc)) >= nc)  # the rounding case is exercised
+    cell = orc.cell_index(x, L, nc)
+    cx = cell % nc[0]
+    cy = (cell // nc[0]) % nc[1]
+    cz = cell // (nc[0] * nc[1])
+    assert cx[0] == nc[0] - 1 and cy[1] == nc[1] - 1 and cz[2] == nc[2] - 1
+    assert cell[3] == 0
