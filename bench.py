@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark of the short-range LJ MD hot path on one MI355X.
+
+A step is one velocity-Verlet MD step of the whole path: half kick + drift +
+wrap, the binned re-sort and Verlet-list rebuild every 20 steps, LJ forces
+with per-atom energy, energy and virial, and the second half kick with the
+kinetic energy.  Workload: the 500,000-atom dense LJ liquid (fcc 50^3 cells
+at rho* = 0.8442, T* = 1.44, rc 2.5, skin 0.3, dt 0.005), synthetic and
+seeded, inputs resident in HBM before the timed region.
+
+Prints ONE JSON line: the mixed-precision path's atom-steps/s (headline), the
+FP64 path beside it, backward/forward time ratios (32k force matching and the
+256k checkpointed trajectory), the dominant kernel's roofline figures and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# HBM bytes per dispatch of the force kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
+# scaled by the copy-kernel calibration; None until counters are taken for this kernel.
+FORCE_TRAFFIC = None
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="lj500k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the headline path only (no FP64 run, no bwd/fwd ratios)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of the oracle's CPU sample")
+    return ap.parse_args()
+
+
+def md_run(w, s, precision, steps, warmup, dev):
+    """Time `steps` MD steps after `warmup`; returns (seconds, force-call ms list, sim)."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=precision, kind=ops.FULL, dt=w.dt,
+                   rebuild_every=w.rebuild_every, device=dev)
+    sim.load(s["x"], s["v"])
+    sim.step(warmup)
+    timer = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, force_timer=timer)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    force_ms = [a.elapsed_time(b) for a, b in timer]
+    return t1 - t0, force_ms, sim
+
+
+def event_time(fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bwd_fwd_forcematching(dev, reps=100):
+    """Force-matching workload (32,000 atoms, two types): t(force_backward)/t(compute_forces)."""
+    import numpy as np
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import autograd, ops
+    w = li.WORKLOADS["lj32k_fm"]
+    x, ty = li.positions(w), li.types(w)
+    eps, sig = (torch.as_tensor(a, device=dev) for a in li.params(w))
+    out = {}
+    for name, prec in (("mixed", ops.MIXED), ("fp64", ops.FP64)):
+        fc = autograd.ForceContext(w.box, x, ty, rc=w.rc, skin=w.skin, precision=prec, device=dev)
+        g = torch.as_tensor(np.random.default_rng(0).normal(size=x.shape), device=dev)
+        F = torch.empty_like(fc.x)
+        gx = torch.empty_like(fc.x)
+        ge, gs = torch.empty_like(eps), torch.empty_like(eps)
+        wsf = torch.empty(ops.workspace_bytes(ops.OP_FORCES, x.shape[0]), dtype=torch.uint8,
+                          device=dev)
+        wsb = torch.empty(ops.workspace_bytes(ops.OP_BACKWARD, x.shape[0], 0, 2),
+                          dtype=torch.uint8, device=dev)
+        nl = fc.nl
+        tf = event_time(lambda: ops.compute_forces(w.box, prec, ops.FULL, w.rc, eps, sig, fc.x,
+                                                   fc.types, nl.nbr, nl.nnbr, nl.maxn, F=F,
+                                                   want_energy=False, ws=wsf), reps)
+        tb = event_time(lambda: ops.force_backward(w.box, prec, w.rc, eps, sig, fc.x, fc.types,
+                                                   nl.nbr, nl.nnbr, nl.maxn, g, gx=gx, geps=ge,
+                                                   gsigma=gs, ws=wsb), reps)
+        out[name] = {"fwd_ms": round(tf, 5), "bwd_ms": round(tb, 5), "ratio": round(tb / tf, 3)}
+    return out
+
+
+def bwd_fwd_trajectory(dev):
+    """Backprop through 20 steps of the 256,000-atom two-type system (mixed), checkpoints
+    every 5: trajectory-level t(forward + checkpointed reverse) / t(forward) and the
+    kernel-level ratio on the same list."""
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import ops, trajectory
+    w = li.WORKLOADS["lj256k_traj"]
+    x0, v0, ty = li.positions(w), li.velocities(w), li.types(w)
+    eps, sig = li.params(w)
+    et, st = li.perturbed_params(w)
+    xref = trajectory.run_trajectory(w.box, x0, v0, ty, et, st, steps=w.steps, precision=ops.MIXED,
+                                     device=dev)
+    sim = trajectory._forward_sim(w.box, x0, v0, ty, eps, sig, w.rc, w.skin, w.dt, 1.0,
+                                  ops.MIXED, w.steps, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.steps, energy=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref.cpu().numpy(),
+                                       steps=w.steps, checkpoint_every=w.checkpoint_every,
+                                       precision=ops.MIXED, device=dev, verify_recompute=False)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    s2 = r.sim
+    nl = s2.nl
+    g = torch.randn_like(s2.x)
+    tf = event_time(lambda: ops.compute_forces(w.box, ops.MIXED, ops.FULL, w.rc, s2.eps, s2.sigma,
+                                               s2.x, s2.types, nl.nbr, nl.nnbr, nl.maxn,
+                                               want_energy=False), 20)
+    tb = event_time(lambda: ops.force_backward(w.box, ops.MIXED, w.rc, s2.eps, s2.sigma, s2.x,
+                                               s2.types, nl.nbr, nl.nnbr, nl.maxn, g), 20)
+    return {"steps": w.steps, "checkpoint_every": w.checkpoint_every,
+            "forward_s": round(t_fwd, 5), "forward_plus_reverse_s": round(t_all, 5),
+            "trajectory_ratio": round(t_all / t_fwd, 3),
+            "kernel_fwd_ms": round(tf, 5), "kernel_bwd_ms": round(tb, 5),
+            "kernel_ratio": round(tb / tf, 3)}
+
+
+def cpu_baseline(w, s, target_s):
+    """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input."""
+    import numpy as np
+    import oracle
+    n = w.natoms
+    rng = np.random.default_rng(0)
+    probe = np.sort(rng.choice(n, 256, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces(s["x"], w.box, w.rc, sel=probe)
+    per_atom = (time.perf_counter() - t0) / probe.size
+    m = int(min(n, max(512, target_s / max(per_atom, 1e-9))))
+    rows = np.sort(rng.choice(n, m, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces(s["x"], w.box, w.rc, sel=rows)
+    dt = time.perf_counter() - t0
+    return {"value": round(m / dt, 3), "unit": "atom-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"all-pairs FP64 forces+energy for {m} sampled atoms of the {n}-atom "
+                      f"input (one force evaluation each, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(spatial decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import _lib, ops
+
+    dev = torch.device("cuda:0")
+    _lib.load()
+    w = li.WORKLOADS[args.workload]
+    s = li.make_system(w)
+    n = w.natoms
+    log(f"[bench] workload {w.name}: {n} atoms, box {w.box[0]:.4f}, mixed path, "
+        f"{args.warmup} warmup + {args.steps} timed steps")
+    t_mixed, fms, sim = md_run(w, s, ops.MIXED, args.steps, args.warmup, dev)
+    value = n * args.steps / t_mixed
+    nbar = float(sim.nl.nnbr.double().mean().item())
+    force_ms = statistics.mean(fms)
+    force_bytes = n * (4.0 * nbar + 24 + 24 + 8 + 4)
+    achieved = force_bytes / (force_ms * 1e-3) / 1e9
+    th = sim.thermo()
+    log(f"[bench] mixed: {t_mixed * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s, "
+        f"force call {force_ms * 1e3:.1f} us, mean list {nbar:.2f}, T {th['temp']:.4f}")
+    line = {
+        "metric": "atom-steps/s LJ force+neighbor, mixed vs FP64, 500k atoms; bwd/fwd time ratio",
+        "value": round(value, 1), "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed: f64 displacement/cutoff/accumulation, f32 pair math",
+        "data": "synthetic (seeded jittered fcc LJ liquid, Maxwell velocities)",
+        "config": {"workload": f"{w.name}: fcc {w.cells}^3 cells, {n} atoms, rho 0.8442, "
+                               f"T 1.44, rc 2.5, skin 0.3, dt 0.005, rebuild every 20, full list",
+                   "natoms": n, "precision": "mixed", "list": "full",
+                   "mean_list_length": round(nbar, 3), "maxn": sim.nl.maxn},
+        "roofline": {"bound": "hbm", "kernel": "k_force_full<mixed> (+ energy/virial column sum)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": FORCE_TRAFFIC,
+                     "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
+    }
+    if not args.no_extras:
+        t64, f64ms, sim64 = md_run(w, s, ops.FP64, args.steps, args.warmup, dev)
+        line["fp64"] = {"value": round(n * args.steps / t64, 1), "unit": "atom-steps/s",
+                        "ms_per_step": round(t64 * 1e3 / args.steps, 5),
+                        "force_call_us": round(statistics.mean(f64ms) * 1e3, 3),
+                        "mixed_over_fp64": round(t64 / t_mixed, 4)}
+        log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
+        line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),
+                           "trajectory_256k": bwd_fwd_trajectory(dev)}
+        log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample")
+        line["cpu_baseline"] = cpu_baseline(w, s, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    _ = np
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * ljmd.h -- C ABI of the MI355X (gfx950) short-range Lennard-Jones MD hot path.
+ *
+ * The paper (Introduction; Cabana "Particle Sorting", "Neighbor List
+ * Creation", "Parallel Loops" and "CabanaMD" subsections) splits a short-range
+ * MD timestep into: sort particles by spatial bin, build Verlet neighbor lists
+ * from a distance criterion on a binning grid, evaluate the per-particle force
+ * kernel over the neighbor list, and propagate positions; the library side
+ * owns sorting, lists and neighbor indexing, the application side owns the
+ * force model and integration, and the library is callable from C through
+ * memory-wrapping interfaces over caller-owned data.  This header is that
+ * boundary:
+ *
+ *   ljmd_bin              counting sort of atoms into cells (cell-major, id-minor)
+ *   ljmd_build_neighbors  Verlet lists over the 27-cell stencil (full or half)
+ *   ljmd_compute_forces   12-6 LJ forces, per-atom energy, energy + virial
+ *   ljmd_integrate        velocity-Verlet half kick + drift + wrap / half kick
+ *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
+ *
+ * plus a few helpers (grid, workspace sizes, errors) and the elementwise
+ * steps of the discrete trajectory adjoint.
+ *
+ * Conventions, common to every call:
+ *  - Units: LJ reduced units, k_B = 1.  Orthorhombic periodic box [0, L).
+ *  - Positions, velocities, forces: FP64, [n][3] row-major (x, y, z per atom).
+ *  - Every array argument is a DEVICE pointer owned by the caller, except
+ *    where marked (host).  The library allocates and frees nothing and keeps
+ *    no state between calls.  Outputs never alias inputs unless stated.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).  All
+ *    device work is enqueued asynchronously on it; no call synchronizes.
+ *  - Return value: LJMD_OK or an error code; no exception crosses the ABI.
+ *    ljmd_last_error() gives a thread-local message for the last failure.
+ *  - Minimum image: for positions within L/2 of [0, L), d = x_i - x_j folded
+ *    to its representative nearest zero per component.  Requires
+ *    rlist <= (1/2 - 1e-9) * min(L) (else LJMD_EBOX).
+ *  - r^2 = (dx*dx + dy*dy) + dz*dz in FP64 without contraction; the neighbor
+ *    test is r^2 < rlist*rlist and the force cutoff r^2 < rc*rc (strict).
+ *  - Atom counts are limited to n < 2^31 - 64.
+ */
+#ifndef LJMD_H
+#define LJMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define LJMD_OK 0
+#define LJMD_EINVAL 1     /* null pointer, bad size, bad enum, non-positive rc/dt/mass */
+#define LJMD_EBOX 2       /* non-positive box edge or rlist too large for minimum image */
+#define LJMD_EWORKSPACE 3 /* workspace or cell buffer smaller than required */
+#define LJMD_EHIP 4       /* HIP launch/runtime error; see ljmd_last_error() */
+
+/* ---- enums ---- */
+#define LJMD_FP64 0   /* all pair arithmetic in FP64 */
+#define LJMD_MIXED 1  /* FP64 displacement, r^2 and cutoff test; FP32 pair math;
+                         FP64 accumulation of forces, energies, virial, gradients */
+#define LJMD_FULL 0   /* every ordered pair (i, j): each atom owns all its neighbors */
+#define LJMD_HALF 1   /* each unordered pair once, owned by the lower sorted index */
+#define LJMD_KICK_DRIFT 0 /* v += dt/2 F/m; x += dt v; wrap x into [0, L) */
+#define LJMD_KICK 1       /* v += dt/2 F/m */
+
+/* workspace queries (ljmd_workspace_bytes) */
+#define LJMD_OP_BIN 0
+#define LJMD_OP_FORCES 1
+#define LJMD_OP_BACKWARD 2
+#define LJMD_OP_INTEGRATE 3
+#define LJMD_OP_LOSS 4
+
+#define LJMD_MAX_TYPES 8
+#define LJMD_TILE 64 /* atoms per neighbor-list tile: one wavefront */
+
+typedef struct {
+  double L[3]; /* box edges; periodic in all three dimensions, origin at 0 */
+} ljmd_box;
+
+/* Cell grid for binning at list cutoff rlist (host only, no device work):
+ * nc[k] = floor(L[k]/rlist), reduced by one while L[k]/nc[k] is not above
+ * rlist by a relative 1e-10, and at least 1.  The number of cells is
+ * nc[0]*nc[1]*nc[2]; cell (cx, cy, cz) has linear index (cz*nc[1] + cy)*nc[0] + cx.
+ * Errors: LJMD_EINVAL (null), LJMD_EBOX (L <= 0 or rlist too large). */
+int ljmd_grid(const ljmd_box *box, double rlist, int32_t nc[3]);
+
+/* Bytes of device workspace `op` needs for n atoms (ncells: cells of the
+ * grid, used by LJMD_OP_BIN; ntypes: used by LJMD_OP_BACKWARD). 0 on bad op. */
+size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes);
+
+/* Human-readable text for a return code; thread-local detail of the last error. */
+const char *ljmd_error_string(int code);
+const char *ljmd_last_error(void);
+
+/*
+ * ljmd_bin -- re-sort particles by spatial bin (paper: Cabana "Particle
+ * Sorting", geometric binning; Introduction: particles are re-sorted to begin
+ * the next timestep).
+ *
+ * Cell of atom i: c_k = min(floor(x_ik / h_k), nc_k - 1), h_k = L_k / nc_k, with
+ * nc from ljmd_grid(box, rlist).  Output order: cell-major, and inside a cell
+ * ascending id.  The result is a deterministic permutation (it does not
+ * depend on the order of atomic operations inside the sort).
+ *   x_in [n][3]          positions in [0, L) (values outside are clamped to
+ *                        the border cells, which the neighbor search
+ *                        then cannot guarantee to find)
+ *   v_in [n][3]          velocities, or NULL (then v_out is ignored)
+ *   type_in [n]          int32 types, or NULL (then type_out is ignored)
+ *   id_in [n]            int64 unique ids, or NULL (ids := input positions)
+ *   x_out, v_out, type_out, id_out   permuted copies ([n][3], [n][3], [n], [n])
+ *   cell_start [ncells+1] int32: sorted positions [cell_start[c], cell_start[c+1])
+ *                        hold cell c; cell_start[ncells] = n
+ *   cell_cap             length of cell_start; must be >= ncells+1 (else EWORKSPACE)
+ *   ws, ws_bytes         device workspace, >= ljmd_workspace_bytes(LJMD_OP_BIN, n, ncells, 0)
+ */
+int ljmd_bin(const ljmd_box *box, double rlist, int64_t n, const double *x_in,
+             const double *v_in, const int32_t *type_in, const int64_t *id_in, double *x_out,
+             double *v_out, int32_t *type_out, int64_t *id_out, int32_t *cell_start,
+             int64_t cell_cap, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_build_neighbors -- Verlet lists by binning (paper: Cabana "Neighbor
+ * List Creation": distance-criterion lists built on a search grid, dense
+ * storage).  Requires atoms already sorted by ljmd_bin with the SAME box and
+ * rlist (cell_start from that call).
+ *
+ * kind LJMD_FULL: N(i) = { j != i : r^2_ij < rlist^2 }.
+ * kind LJMD_HALF: the pairs of the full relation with j > i (sorted indices).
+ * Storage is tiled ELL, one tile per 64 consecutive sorted atoms:
+ *   neighbor k of atom i is nbr[((i / 64) * maxn + k) * 64 + (i % 64)], k < nnbr[i]
+ * so nbr holds ceil(n/64)*64*maxn int32 (sorted indices).  Order inside a row
+ * is unspecified.
+ *   x          sorted positions [n][3]
+ *   cell_start from ljmd_bin
+ *   maxn       row capacity (>= 1)
+ *   nbr, nnbr  outputs as above; nnbr[i] = min(|N(i)|, maxn)
+ *   max_count  device int32 scalar, overwritten with max_i |N(i)|.  If it
+ *              exceeds maxn after the stream has run, rows were truncated:
+ *              the caller enlarges maxn and calls again (capacity overflow
+ *              is reported on the device, not as a return code).
+ */
+int ljmd_build_neighbors(const ljmd_box *box, double rlist, int kind, int64_t n,
+                         const double *x, const int32_t *cell_start, int32_t maxn,
+                         int32_t *nbr, int32_t *nnbr, int32_t *max_count, void *stream);
+
+/*
+ * ljmd_compute_forces -- 12-6 Lennard-Jones forces over the neighbor list
+ * (paper: CabanaMD's Lennard-Jones short-range force kernel, written as a
+ * neighbor parallel loop; Introduction: per-particle forces from the
+ * neighborhood description).
+ *
+ * For each listed pair with r^2 < rc^2 and parameters (eps, sigma) of the
+ * type pair:  u = 4 eps [(sigma/r)^12 - (sigma/r)^6],  s = -u'(r)/r,
+ *   F_i = sum_j s d_ij,  e_i = 1/2 sum_j u_ij,
+ *   ev = { E = sum_i e_i, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz },  W = 1/2 sum_i sum_j d_ij (s d_ij)^T
+ * (truncated, unshifted; one absolute rc for every type pair).
+ *   precision  LJMD_FP64 or LJMD_MIXED
+ *   kind       list kind built by ljmd_build_neighbors.  FULL: one lane per
+ *              atom, no atomics, bitwise deterministic.  HALF: Newton's third
+ *              law with FP64 atomic updates (summation order not fixed).
+ *   ntypes     1..LJMD_MAX_TYPES; eps_packed/sigma_packed: device FP64
+ *              [ntypes(ntypes+1)/2], upper triangle row-major:
+ *              entry (a, b), a <= b, at a*ntypes - a(a-1)/2 + (b - a)
+ *   type       int32 [n] sorted types, or NULL when ntypes == 1
+ *   F          [n][3] overwritten
+ *   e_atom     [n] overwritten, or NULL
+ *   ev         [7] overwritten, or NULL
+ *   ws         >= ljmd_workspace_bytes(LJMD_OP_FORCES, n, 0, ntypes)
+ */
+int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
+                        int32_t ntypes, const double *eps_packed, const double *sigma_packed,
+                        int64_t n, const double *x, const int32_t *type, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, double *F, double *e_atom,
+                        double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_integrate -- velocity Verlet (paper: CabanaMD keeps the position
+ * integration in the application; Introduction: forces propagate particles
+ * to new positions).  In place on x and v.
+ *   stage LJMD_KICK_DRIFT: v += dt/2 F/m; x += dt v; wrap each component:
+ *         if x >= L: x -= L, else if x < 0: x += L; then if x >= L: x -= L
+ *   stage LJMD_KICK:       v += dt/2 F/m
+ *   ke    device FP64 scalar receiving 1/2 m sum v^2 after the update, or NULL
+ *   ws    >= ljmd_workspace_bytes(LJMD_OP_INTEGRATE, n, 0, 0) when ke != NULL
+ */
+int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64_t n,
+                   double *x, double *v, const double *F, double *ke, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_force_backward -- adjoint of ljmd_compute_forces (FULL list only).
+ * For a cotangent g = dL/dF [n][3], with the list and the pair set r < rc held
+ * fixed (the truncation is not differentiated), K_ij = s I + 2 s' d d^T and
+ * s' = ds/d(r^2):
+ *   gx_i     = sum_j K_ij (g_i - g_j)
+ *   geps[p]  = sum over ordered pairs (i, j) of type pair p of g_i . d_ij ds/deps
+ *   gsigma[p]= the same with ds/dsigma
+ *   accumulate  0: gx, geps, gsigma are overwritten; 1: added to
+ *   ws          >= ljmd_workspace_bytes(LJMD_OP_BACKWARD, n, 0, ntypes)
+ * Other arguments as in ljmd_compute_forces.  Bitwise deterministic.
+ */
+int ljmd_force_backward(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                        const double *eps_packed, const double *sigma_packed, int64_t n,
+                        const double *x, const int32_t *type, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, const double *g, double *gx,
+                        double *geps, double *gsigma, int accumulate, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* ---- elementwise steps of the discrete velocity-Verlet adjoint ----
+ *
+ * Reverse of one step (x_n, v_n) -> (x_{n+1}, v_{n+1}) once the VJP at
+ * x_{n+1} has been folded into xbar:  vbar += dt * xbar, then the VJP at x_n
+ * with cotangent w * dt * vbar (w = 1 where the two half kicks meeting at an
+ * interior x_n are merged, 1/2 at the first step).
+ * ljmd_adjoint_kick: vbar += dt * xbar; g = w * dt * vbar.  [n][3] each. */
+int ljmd_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
+                      double *g, void *stream);
+
+/* Trajectory loss on final positions: d = minimum image of (x - xref) (equal
+ * to the unwrapped difference while the two trajectories stay within L/2),
+ * xbar = d, loss = 1/2 sum |d|^2 (device scalar; deterministic reduction).
+ * ws >= ljmd_workspace_bytes(LJMD_OP_LOSS, n, 0, 0). */
+int ljmd_traj_loss(const ljmd_box *box, int64_t n, const double *x, const double *xref,
+                   double *xbar, double *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Row scatter through ids: dst[id[k]] = src[k] for rows of `width` doubles
+ * (maps sorted-order results back to the caller's atom order).  Rows whose
+ * id lies outside [0, n) are skipped. */
+int ljmd_scatter_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                      double *dst, void *stream);
+
+/* Row gather through ids: dst[k] = src[id[k]] (brings caller-order data into
+ * sorted order).  Rows whose id lies outside [0, n) are left untouched. */
+int ljmd_gather_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                     double *dst, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJMD_H */

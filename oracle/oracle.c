@@ -44,6 +44,19 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads an OpenMP parallel region of the oracle uses (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 static int packed_index(int a, int b, int T) {
   if (a > b) { int t = a; a = b; b = t; }
   return a * T - a * (a - 1) / 2 + (b - a);

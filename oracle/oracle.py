@@ -52,6 +52,7 @@ def lib():
                                         _VP, _D, _D, _D, _D]
             L.orc_kick_drift.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _VP]
             L.orc_kick.argtypes = [_i64, _D, _D, _dbl, _dbl]
+            L.orc_num_threads.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -73,6 +74,11 @@ def ntypes_of(eps) -> int:
     t = int(round((np.sqrt(8 * p + 1) - 1) / 2))
     assert t * (t + 1) // 2 == p, "packed parameter length must be T(T+1)/2"
     return t
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())
 
 
 # ------------------------------------------------------------------ binning --

@@ -1,0 +1,307 @@
+// extern "C" entry points of libljmd: argument validation, dispatch to the
+// gfx950 kernels, error reporting.  Declared and documented in ljmd.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "common.h"
+
+namespace ljmd {
+
+// kernels' host launchers (one per source file)
+size_t bin_workspace(int64_t n, int64_t ncells);
+int launch_bin(const GridK &g, int64_t n, const double *x_in, const double *v_in,
+               const int32_t *type_in, const int64_t *id_in, double *x_out, double *v_out,
+               int32_t *type_out, int64_t *id_out, int32_t *cell_start, void *ws, hipStream_t st);
+int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n, const double *x,
+                 const int32_t *cell_start, int32_t maxn, int32_t *nbr, int32_t *nnbr,
+                 int32_t *max_count, hipStream_t st);
+size_t force_workspace(int64_t n);
+int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t ntypes,
+                  const double *eps, const double *sig, int64_t n, const double *x,
+                  const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                  double *F, double *e_atom, double *ev, void *ws, hipStream_t st);
+size_t bwd_workspace(int64_t n, int32_t ntypes);
+int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                    const double *sig, int64_t n, const double *x, const int32_t *type,
+                    const int32_t *nbr, const int32_t *nnbr, int32_t maxn, const double *g,
+                    double *gx, double *geps, double *gsig, int accumulate, void *ws,
+                    hipStream_t st);
+size_t stream_workspace(int64_t n);
+int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n, double *x,
+                     double *v, const double *F, double *ke, void *ws, hipStream_t st);
+int launch_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
+                        double *g, hipStream_t st);
+int launch_loss(const BoxK &b, int64_t n, const double *x, const double *xref, double *xbar,
+                double *loss, void *ws, hipStream_t st);
+int launch_scatter_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                        double *dst, hipStream_t st);
+int launch_gather_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                       double *dst, hipStream_t st);
+
+namespace {
+thread_local char g_msg[512] = "";
+constexpr int64_t kMaxAtoms = (int64_t)2147483647 - 64;
+}  // namespace
+
+int set_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(LJMD_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return LJMD_OK;
+}
+
+BoxK make_box(const ljmd_box *b) {
+  BoxK k;
+  for (int d = 0; d < 3; ++d) {
+    k.L[d] = b->L[d];
+    k.invL[d] = 1.0 / b->L[d];
+  }
+  return k;
+}
+
+static int check_box(const ljmd_box *b) {
+  if (!b) return set_error(LJMD_EINVAL, "box is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!(b->L[d] > 0.0) || !isfinite(b->L[d]))
+      return set_error(LJMD_EBOX, "box edge L[%d] = %g must be finite and > 0", d, b->L[d]);
+  return LJMD_OK;
+}
+
+static int check_cutoff(const ljmd_box *b, double r, const char *name) {
+  if (!(r > 0.0) || !isfinite(r)) return set_error(LJMD_EINVAL, "%s = %g must be > 0", name, r);
+  double lmin = fmin(b->L[0], fmin(b->L[1], b->L[2]));
+  if (r > (0.5 - 1e-9) * lmin)
+    return set_error(LJMD_EBOX, "%s = %g too large for minimum image in a box of edge %g", name,
+                     r, lmin);
+  return LJMD_OK;
+}
+
+int make_grid(const ljmd_box *b, double rlist, GridK *g) {
+  int64_t total = 1;
+  for (int d = 0; d < 3; ++d) {
+    int64_t c = (int64_t)floor(b->L[d] / rlist);
+    while (c > 1 && b->L[d] / (double)c < rlist * (1.0 + 1e-10)) --c;
+    if (c < 1) c = 1;
+    if (c > (int64_t)1 << 20) return set_error(LJMD_EBOX, "grid too fine (%lld cells)", (long long)c);
+    g->nc[d] = (int32_t)c;
+    g->h[d] = b->L[d] / (double)c;
+    total *= c;
+  }
+  if (total > ((int64_t)1 << 30)) return set_error(LJMD_EBOX, "grid has %lld cells", (long long)total);
+  g->ncells = (int32_t)total;
+  return LJMD_OK;
+}
+
+static int check_n(int64_t n) {
+  if (n < 0 || n > kMaxAtoms) return set_error(LJMD_EINVAL, "n = %lld out of range", (long long)n);
+  return LJMD_OK;
+}
+
+static int check_ws(void *ws, size_t have, size_t need) {
+  if (need > 0 && (!ws || have < need))
+    return set_error(LJMD_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws ? have : (size_t)0);
+  return LJMD_OK;
+}
+
+static int check_params(int32_t ntypes, const double *eps, const double *sig, const int32_t *type,
+                        int64_t n) {
+  if (ntypes < 1 || ntypes > LJMD_MAX_TYPES)
+    return set_error(LJMD_EINVAL, "ntypes = %d outside [1, %d]", ntypes, LJMD_MAX_TYPES);
+  if (!eps || !sig) return set_error(LJMD_EINVAL, "eps/sigma is NULL");
+  if (ntypes > 1 && n > 0 && !type) return set_error(LJMD_EINVAL, "type is NULL with ntypes > 1");
+  return LJMD_OK;
+}
+
+}  // namespace ljmd
+
+using namespace ljmd;
+
+#define LJMD_TRY(expr)             \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ != LJMD_OK) return rc_; \
+  } while (0)
+
+extern "C" {
+
+const char *ljmd_error_string(int code) {
+  switch (code) {
+    case LJMD_OK: return "ok";
+    case LJMD_EINVAL: return "invalid argument";
+    case LJMD_EBOX: return "invalid box or cutoff";
+    case LJMD_EWORKSPACE: return "workspace or buffer too small";
+    case LJMD_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+const char *ljmd_last_error(void) { return g_msg; }
+
+int ljmd_grid(const ljmd_box *box, double rlist, int32_t nc[3]) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rlist, "rlist"));
+  if (!nc) return set_error(LJMD_EINVAL, "nc is NULL");
+  GridK g;
+  LJMD_TRY(make_grid(box, rlist, &g));
+  for (int d = 0; d < 3; ++d) nc[d] = g.nc[d];
+  return LJMD_OK;
+}
+
+size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
+  if (n < 0) n = 0;
+  switch (op) {
+    case LJMD_OP_BIN: return bin_workspace(n, ncells > 0 ? ncells : 1);
+    case LJMD_OP_FORCES: return force_workspace(n);
+    case LJMD_OP_BACKWARD:
+      return bwd_workspace(n, ntypes < 1 ? 1 : (ntypes > LJMD_MAX_TYPES ? LJMD_MAX_TYPES : ntypes));
+    case LJMD_OP_INTEGRATE:
+    case LJMD_OP_LOSS: return stream_workspace(n);
+    default: return 0;
+  }
+}
+
+int ljmd_bin(const ljmd_box *box, double rlist, int64_t n, const double *x_in,
+             const double *v_in, const int32_t *type_in, const int64_t *id_in, double *x_out,
+             double *v_out, int32_t *type_out, int64_t *id_out, int32_t *cell_start,
+             int64_t cell_cap, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rlist, "rlist"));
+  LJMD_TRY(check_n(n));
+  GridK g;
+  LJMD_TRY(make_grid(box, rlist, &g));
+  if (!cell_start) return set_error(LJMD_EINVAL, "cell_start is NULL");
+  if (cell_cap < (int64_t)g.ncells + 1)
+    return set_error(LJMD_EWORKSPACE, "cell_start holds %lld entries, %d needed",
+                     (long long)cell_cap, g.ncells + 1);
+  if (n > 0) {
+    if (!x_in || !x_out || !id_out) return set_error(LJMD_EINVAL, "x_in/x_out/id_out is NULL");
+    if (v_in && !v_out) return set_error(LJMD_EINVAL, "v_out is NULL while v_in is given");
+    if (type_in && !type_out) return set_error(LJMD_EINVAL, "type_out is NULL while type_in is given");
+  }
+  LJMD_TRY(check_ws(ws, ws_bytes, bin_workspace(n, g.ncells)));
+  return launch_bin(g, n, x_in, v_in, type_in, id_in, x_out, v_out, type_out, id_out, cell_start,
+                    ws, (hipStream_t)stream);
+}
+
+int ljmd_build_neighbors(const ljmd_box *box, double rlist, int kind, int64_t n,
+                         const double *x, const int32_t *cell_start, int32_t maxn,
+                         int32_t *nbr, int32_t *nnbr, int32_t *max_count, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rlist, "rlist"));
+  LJMD_TRY(check_n(n));
+  if (kind != LJMD_FULL && kind != LJMD_HALF) return set_error(LJMD_EINVAL, "bad kind %d", kind);
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (!max_count || !cell_start) return set_error(LJMD_EINVAL, "max_count/cell_start is NULL");
+  if (n > 0 && (!x || !nbr || !nnbr)) return set_error(LJMD_EINVAL, "x/nbr/nnbr is NULL");
+  if ((n + LJMD_TILE - 1) / LJMD_TILE * LJMD_TILE * (int64_t)maxn > ((int64_t)1 << 40))
+    return set_error(LJMD_EINVAL, "list of n = %lld rows x maxn = %d is too large", (long long)n, maxn);
+  GridK g;
+  LJMD_TRY(make_grid(box, rlist, &g));
+  return launch_build(g, make_box(box), rlist, kind, n, x, cell_start, maxn, nbr, nnbr, max_count,
+                      (hipStream_t)stream);
+}
+
+int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
+                        int32_t ntypes, const double *eps_packed, const double *sigma_packed,
+                        int64_t n, const double *x, const int32_t *type, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, double *F, double *e_atom,
+                        double *ev, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  if (kind != LJMD_FULL && kind != LJMD_HALF) return set_error(LJMD_EINVAL, "bad kind %d", kind);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (n > 0 && (!x || !nbr || !nnbr || !F)) return set_error(LJMD_EINVAL, "x/nbr/nnbr/F is NULL");
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? force_workspace(n) : 0));
+  return launch_forces(make_box(box), precision, kind, rc, ntypes, eps_packed, sigma_packed, n, x,
+                       type, nbr, nnbr, maxn, F, e_atom, ev, ws, (hipStream_t)stream);
+}
+
+int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64_t n,
+                   double *x, double *v, const double *F, double *ke, void *ws,
+                   size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_n(n));
+  if (stage != LJMD_KICK_DRIFT && stage != LJMD_KICK)
+    return set_error(LJMD_EINVAL, "bad stage %d", stage);
+  if (!isfinite(dt) || dt == 0.0) return set_error(LJMD_EINVAL, "dt = %g", dt);
+  if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g", mass);
+  if (stage == LJMD_KICK_DRIFT) LJMD_TRY(check_box(box));
+  if (n > 0 && (!v || !F || (stage == LJMD_KICK_DRIFT && !x)))
+    return set_error(LJMD_EINVAL, "x/v/F is NULL");
+  if (ke) LJMD_TRY(check_ws(ws, ws_bytes, stream_workspace(n)));
+  BoxK b = stage == LJMD_KICK_DRIFT ? make_box(box) : BoxK{};
+  return launch_integrate(stage, dt, mass, b, n, x, v, F, ke, ws, (hipStream_t)stream);
+}
+
+int ljmd_force_backward(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                        const double *eps_packed, const double *sigma_packed, int64_t n,
+                        const double *x, const int32_t *type, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, const double *g, double *gx,
+                        double *geps, double *gsigma, int accumulate, void *ws,
+                        size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (!geps || !gsigma) return set_error(LJMD_EINVAL, "geps/gsigma is NULL");
+  if (n > 0 && (!x || !nbr || !nnbr || !g || !gx))
+    return set_error(LJMD_EINVAL, "x/nbr/nnbr/g/gx is NULL");
+  if (accumulate != 0 && accumulate != 1)
+    return set_error(LJMD_EINVAL, "accumulate = %d must be 0 or 1", accumulate);
+  LJMD_TRY(check_ws(ws, ws_bytes, bwd_workspace(n, ntypes)));
+  return launch_backward(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x,
+                         type, nbr, nnbr, maxn, g, gx, geps, gsigma, accumulate, ws,
+                         (hipStream_t)stream);
+}
+
+int ljmd_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
+                      double *g, void *stream) {
+  LJMD_TRY(check_n(n));
+  if (!isfinite(dt) || !isfinite(w)) return set_error(LJMD_EINVAL, "dt/w not finite");
+  if (n > 0 && (!xbar || !vbar || !g)) return set_error(LJMD_EINVAL, "xbar/vbar/g is NULL");
+  return launch_adjoint_kick(n, dt, w, xbar, vbar, g, (hipStream_t)stream);
+}
+
+int ljmd_traj_loss(const ljmd_box *box, int64_t n, const double *x, const double *xref,
+                   double *xbar, double *loss, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_n(n));
+  if (!loss) return set_error(LJMD_EINVAL, "loss is NULL");
+  if (n > 0 && (!x || !xref || !xbar)) return set_error(LJMD_EINVAL, "x/xref/xbar is NULL");
+  LJMD_TRY(check_ws(ws, ws_bytes, stream_workspace(n)));
+  return launch_loss(make_box(box), n, x, xref, xbar, loss, ws, (hipStream_t)stream);
+}
+
+int ljmd_scatter_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                      double *dst, void *stream) {
+  LJMD_TRY(check_n(n));
+  if (width < 1 || width > 1024) return set_error(LJMD_EINVAL, "width = %d", width);
+  if (n > 0 && (!id || !src || !dst)) return set_error(LJMD_EINVAL, "id/src/dst is NULL");
+  return launch_scatter_rows(n, width, id, src, dst, (hipStream_t)stream);
+}
+
+int ljmd_gather_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
+                     double *dst, void *stream) {
+  LJMD_TRY(check_n(n));
+  if (width < 1 || width > 1024) return set_error(LJMD_EINVAL, "width = %d", width);
+  if (n > 0 && (!id || !src || !dst)) return set_error(LJMD_EINVAL, "id/src/dst is NULL");
+  return launch_gather_rows(n, width, id, src, dst, (hipStream_t)stream);
+}
+
+}  // extern "C"

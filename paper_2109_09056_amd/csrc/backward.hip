@@ -1,0 +1,279 @@
+// Adjoint (vector-Jacobian product) of the Lennard-Jones forces over the FULL
+// tiled-ELL list, gfx950.
+//
+// With F_i = sum_j s(r^2_ij) d_ij, a cotangent g on the forces and the pair
+// set held fixed:
+//   dL/dx_i = sum_j K_ij (g_i - g_j),   K_ij = s I + 2 s' d d^T,  s' = ds/d(r^2)
+//   dL/dp   = sum_i sum_j g_i . d_ij ds_ij/dp      (p = eps or sigma of the type pair)
+// Expanding s = ri2 sr6 (48 eps sr6 - 24 eps) with t = ri2 sr6 = sigma^6 r^-8:
+//   s'       = t ri2 (-336 eps sr6 + 96 eps)
+//   ds/deps  = t (48 sr6 - 24)
+//   ds/dsig  = t (576 eps/sigma sr6 - 144 eps/sigma)
+// K_ij is symmetric in (i, j), so the position gradient is a gather over the
+// row of atom i -- one lane per atom, no atomics.  Parameter gradients are
+// accumulated per lane by the neighbor's type, reduced per block by the
+// lane's own type in a fixed order, and summed over blocks by one column-sum
+// launch: the whole adjoint is bitwise reproducible.
+#include "common.h"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+
+struct BwdArgs {
+  BoxK b;
+  double rc2;
+  int32_t ntypes;
+  const double *eps;
+  const double *sig;
+  int32_t n;
+  const double *x;
+  const int32_t *type;
+  const int32_t *nbr;
+  const int32_t *nnbr;
+  int32_t maxn;
+  const double *g;
+  double *gx;
+  int accumulate;
+  double *partial;  // [nblk][2 T T]: (eps | sigma) x (type of i) x (type of j)
+};
+
+// sigma^2, 48 eps, 24 eps, -336 eps, 96 eps, 576 eps/sigma, 144 eps/sigma
+struct BCoef {
+  double sig2, c12, c6, d12, d6, q12, q6;
+};
+
+__device__ __forceinline__ BCoef bcoef(const double *eps, const double *sig, int p) {
+  const double e = eps[p], s = sig[p];
+  return BCoef{s * s, 48.0 * e, 24.0 * e, -336.0 * e, 96.0 * e, 576.0 * e / s, 144.0 * e / s};
+}
+
+struct PairB {
+  double s, sp, dse, dss;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ PairB pair_b(double r2, const BCoef &c) {
+  PairB o;
+  if constexpr (MIXED) {
+    const float ri2 = recip32((float)r2);
+    const float sr2 = (float)c.sig2 * ri2;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float t = ri2 * sr6;
+    o.s = (double)(t * __builtin_fmaf((float)c.c12, sr6, -(float)c.c6));
+    o.sp = (double)(t * ri2 * __builtin_fmaf((float)c.d12, sr6, (float)c.d6));
+    o.dse = (double)(t * __builtin_fmaf(48.0f, sr6, -24.0f));
+    o.dss = (double)(t * __builtin_fmaf((float)c.q12, sr6, -(float)c.q6));
+  } else {
+    const double ri2 = recip64(r2);
+    const double sr2 = c.sig2 * ri2;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double t = ri2 * sr6;
+    o.s = t * __builtin_fma(c.c12, sr6, -c.c6);
+    o.sp = t * ri2 * __builtin_fma(c.d12, sr6, c.d6);
+    o.dse = t * __builtin_fma(48.0, sr6, -24.0);
+    o.dss = t * __builtin_fma(c.q12, sr6, -c.q6);
+  }
+  return o;
+}
+
+// TT: 1 or 2 types with register accumulators; 0: any T <= LJMD_MAX_TYPES with
+// lane-private LDS columns.
+template <bool MIXED, int TT>
+__global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
+  constexpr int MT = LJMD_MAX_TYPES;
+  __shared__ double tab[(TT == 1 ? 1 : MT * MT) * 7];
+  __shared__ double red[kWaves * (TT == 0 ? 1 : 2 * TT * TT)];
+  __shared__ double acc[TT == 0 ? kThreads * 2 * MT : 1];
+  __shared__ int32_t tid_type[TT == 0 ? kThreads : 1];
+  const int T = TT == 0 ? a.ntypes : TT;
+  if constexpr (TT != 1) {
+    for (int q = threadIdx.x; q < T * T; q += kThreads) {
+      const BCoef c = bcoef(a.eps, a.sig, packed_index(q / T, q % T, T));
+      double *t = tab + 7 * q;
+      t[0] = c.sig2; t[1] = c.c12; t[2] = c.c6; t[3] = c.d12; t[4] = c.d6; t[5] = c.q12; t[6] = c.q6;
+    }
+  }
+  if constexpr (TT == 0) {
+    for (int q = 0; q < 2 * MT; ++q) acc[threadIdx.x * 2 * MT + q] = 0.0;
+  }
+  if constexpr (TT != 1) __syncthreads();
+  BCoef c1{};
+  if constexpr (TT == 1) c1 = bcoef(a.eps, a.sig, 0);
+
+  const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+  double ge[TT == 0 ? 1 : TT], gs[TT == 0 ? 1 : TT];
+#pragma unroll
+  for (int q = 0; q < (TT == 0 ? 1 : TT); ++q) ge[q] = gs[q] = 0.0;
+  int ti = 0;
+  if (i < a.n) {
+    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
+                 zi = a.x[3 * (int64_t)i + 2];
+    const double gxi = a.g[3 * (int64_t)i], gyi = a.g[3 * (int64_t)i + 1],
+                 gzi = a.g[3 * (int64_t)i + 2];
+    ti = TT == 1 ? 0 : a.type[i];
+    const int32_t cnt = a.nnbr[i];
+    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
+    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
+    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int32_t k = 0; k < cnt; ++k) {
+      const int32_t j = row[(int64_t)k * kWave];
+      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
+      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
+      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
+      const double r2 = dist2(dx, dy, dz);
+      if (r2 < a.rc2) {
+        int tj = 0;
+        BCoef c;
+        if constexpr (TT == 1) {
+          c = c1;
+        } else {
+          tj = a.type[j];
+          const double *t = tab + 7 * (ti * T + tj);
+          c = BCoef{t[0], t[1], t[2], t[3], t[4], t[5], t[6]};
+        }
+        const PairB p = pair_b<MIXED>(r2, c);
+        const double dgx = gxi - a.g[3 * (int64_t)j];
+        const double dgy = gyi - a.g[3 * (int64_t)j + 1];
+        const double dgz = gzi - a.g[3 * (int64_t)j + 2];
+        const double ddg = __builtin_fma(dx, dgx, __builtin_fma(dy, dgy, dz * dgz));
+        const double q = 2.0 * p.sp * ddg;
+        ax = __builtin_fma(p.s, dgx, __builtin_fma(q, dx, ax));
+        ay = __builtin_fma(p.s, dgy, __builtin_fma(q, dy, ay));
+        az = __builtin_fma(p.s, dgz, __builtin_fma(q, dz, az));
+        const double gid = __builtin_fma(gxi, dx, __builtin_fma(gyi, dy, gzi * dz));
+        if constexpr (TT == 1) {
+          ge[0] = __builtin_fma(gid, p.dse, ge[0]);
+          gs[0] = __builtin_fma(gid, p.dss, gs[0]);
+        } else if constexpr (TT == 2) {
+          const double ve = gid * p.dse, vs = gid * p.dss;
+          if (tj == 0) {
+            ge[0] += ve;
+            gs[0] += vs;
+          } else {
+            ge[1] += ve;
+            gs[1] += vs;
+          }
+        } else {
+          double *col = acc + threadIdx.x * 2 * MT;
+          col[tj] = __builtin_fma(gid, p.dse, col[tj]);
+          col[MT + tj] = __builtin_fma(gid, p.dss, col[MT + tj]);
+        }
+      }
+    }
+    double *o = a.gx + 3 * (int64_t)i;
+    if (a.accumulate) {
+      o[0] += ax;
+      o[1] += ay;
+      o[2] += az;
+    } else {
+      o[0] = ax;
+      o[1] = ay;
+      o[2] = az;
+    }
+  }
+  // per-block sums G[which][ti][tj] in a fixed order
+  double *out = a.partial + (int64_t)blockIdx.x * 2 * T * T;
+  if constexpr (TT == 1) {
+    const double v[2] = {ge[0], gs[0]};
+    block_sum<kWaves, 2>(v, red, out);
+  } else if constexpr (TT == 2) {
+    // layout: [which][a][b] -> which*4 + a*2 + b
+    double v[8];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+          v[w * 4 + aa * 2 + bb] = (ti == aa) ? (w == 0 ? ge[bb] : gs[bb]) : 0.0;
+    block_sum<kWaves, 8>(v, red, out);
+  } else {
+    tid_type[threadIdx.x] = (i < a.n) ? ti : -1;
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * T * T; q += kThreads) {
+      const int w = q / (T * T), aa = (q / T) % T, bb = q % T;
+      double s = 0.0;
+      for (int l = 0; l < kThreads; ++l)
+        if (tid_type[l] == aa) s += acc[l * 2 * MT + w * MT + bb];
+      out[q] = s;
+    }
+  }
+}
+
+// geps[p] (+)= G[0][a][b] + G[0][b][a] (a != b) or G[0][a][a]; gsig likewise.
+__global__ void k_param_finalize(int32_t T, const double *__restrict__ colsums,
+                                 double *__restrict__ geps, double *__restrict__ gsig,
+                                 int accumulate) {
+  const int P = T * (T + 1) / 2;
+  const int q = threadIdx.x;
+  if (q >= 2 * P) return;
+  const int w = q / P, p = q % P;
+  int aa = 0, rem = p;
+  while (rem >= T - aa) {
+    rem -= T - aa;
+    ++aa;
+  }
+  const int bb = aa + rem;
+  double v = colsums[w * T * T + aa * T + bb];
+  if (aa != bb) v += colsums[w * T * T + bb * T + aa];
+  double *o = w == 0 ? geps : gsig;
+  o[p] = accumulate ? o[p] + v : v;
+}
+
+}  // namespace
+
+unsigned bwd_blocks(int64_t n) {
+  const int64_t b = (n + kThreads - 1) / kThreads;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+size_t bwd_workspace(int64_t n, int32_t ntypes) {
+  const size_t cols = 2 * (size_t)ntypes * ntypes;
+  return ((size_t)bwd_blocks(n) + 1) * cols * sizeof(double);
+}
+
+int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                    const double *sig, int64_t n, const double *x, const int32_t *type,
+                    const int32_t *nbr, const int32_t *nnbr, int32_t maxn, const double *g,
+                    double *gx, double *geps, double *gsig, int accumulate, void *ws,
+                    hipStream_t st) {
+  BwdArgs a;
+  a.b = b;
+  a.rc2 = rc * rc;
+  a.ntypes = ntypes;
+  a.eps = eps;
+  a.sig = sig;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.type = type;
+  a.nbr = nbr;
+  a.nnbr = nnbr;
+  a.maxn = maxn;
+  a.g = g;
+  a.gx = gx;
+  a.accumulate = accumulate;
+  a.partial = (double *)ws;
+  const unsigned nblk = bwd_blocks(n);
+  const int cols = 2 * ntypes * ntypes;
+  double *colsums = a.partial + (size_t)nblk * cols;
+  const bool mixed = precision == LJMD_MIXED;
+#define LJMD_VJP(M, TT) k_vjp<M, TT><<<nblk, kThreads, 0, st>>>(a)
+  if (ntypes == 1) {
+    if (mixed) LJMD_VJP(true, 1); else LJMD_VJP(false, 1);
+  } else if (ntypes == 2) {
+    if (mixed) LJMD_VJP(true, 2); else LJMD_VJP(false, 2);
+  } else {
+    if (mixed) LJMD_VJP(true, 0); else LJMD_VJP(false, 0);
+  }
+#undef LJMD_VJP
+  k_colsum<256><<<cols, 256, 0, st>>>(nblk, cols, a.partial, colsums, 1.0, 0);
+  k_param_finalize<<<1, 128, 0, st>>>(ntypes, colsums, geps, gsig, accumulate);
+  return check_launch("ljmd_force_backward");
+}
+
+}  // namespace ljmd

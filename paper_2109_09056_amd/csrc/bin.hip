@@ -1,0 +1,173 @@
+// Counting sort of atoms into binning cells (cell-major, ascending id inside a
+// cell), gfx950.  Paper: Cabana "Particle Sorting" (geometric binning) and the
+// re-sort that begins each MD timestep (Introduction).
+//
+// Four launches:
+//   1. cell id + histogram   one thread per atom, atomic count per cell
+//   2. exclusive scan        one 1024-thread block over all cells
+//   3. scatter               one thread per atom claims a slot in its cell
+//   4. in-cell rank + permute  one wavefront per cell: ids of the cell are
+//                            staged in LDS, each lane ranks its atom among
+//                            them, then copies x, v, type, id to the ranked slot.
+// Step 3's slot order depends on atomic timing; step 4 replaces it by the id
+// order, so the output permutation is deterministic.
+#include "common.h"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kPermWaves = 4;
+constexpr int kStage = 256;  // ids per wavefront staged in LDS
+
+__device__ __forceinline__ int32_t cell_of(const double *xi, const GridK &g) {
+  int32_t c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int32_t ck = (int32_t)floor(xi[k] / g.h[k]);
+    ck = ck > g.nc[k] - 1 ? g.nc[k] - 1 : ck;
+    c[k] = ck < 0 ? 0 : ck;
+  }
+  return (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t m, int32_t val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = val;
+}
+
+__global__ void k_count(int64_t n, const double *__restrict__ x, GridK g,
+                        int32_t *__restrict__ cell, int32_t *__restrict__ counts) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c = cell_of(x + 3 * i, g);
+  cell[i] = c;
+  atomicAdd(&counts[c], 1);
+}
+
+// Exclusive scan of counts[0..m) into start[0..m] (start[m] = total) and a
+// copy into cursor[0..m).  One block; each thread owns a contiguous run.
+__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t m, const int32_t *__restrict__ counts,
+                                                     int32_t *__restrict__ start,
+                                                     int32_t *__restrict__ cursor) {
+  __shared__ int32_t part[kScanThreads];
+  const int t = threadIdx.x;
+  const int32_t per = (m + kScanThreads - 1) / kScanThreads;
+  const int32_t lo = t * per;
+  const int32_t hi = lo + per < m ? lo + per : m;
+  int32_t s = 0;
+  for (int32_t c = lo; c < hi; ++c) s += counts[c];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the per-thread sums
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - s;
+  for (int32_t c = lo; c < hi; ++c) {
+    start[c] = run;
+    cursor[c] = run;
+    run += counts[c];
+  }
+  if (t == kScanThreads - 1) start[m] = part[t];
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell, int32_t *__restrict__ cursor,
+                          int32_t *__restrict__ src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t pos = atomicAdd(&cursor[cell[i]], 1);
+  src[pos] = (int32_t)i;
+}
+
+__device__ __forceinline__ int64_t id_at(const int64_t *id_in, int32_t s) {
+  return id_in ? id_in[s] : (int64_t)s;
+}
+
+__global__ __launch_bounds__(kPermWaves *kWave) void k_permute(
+    int32_t ncells, const int32_t *__restrict__ start, const int32_t *__restrict__ src,
+    const double *__restrict__ x_in, const double *__restrict__ v_in,
+    const int32_t *__restrict__ type_in, const int64_t *__restrict__ id_in,
+    double *__restrict__ x_out, double *__restrict__ v_out, int32_t *__restrict__ type_out,
+    int64_t *__restrict__ id_out) {
+  __shared__ int64_t ids[kPermWaves][kStage];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int32_t c = blockIdx.x * kPermWaves + w;
+  if (c >= ncells) return;  // whole wavefront leaves together; no block barrier below
+  const int32_t s0 = start[c];
+  const int32_t m = start[c + 1] - s0;
+  const bool staged = m <= kStage;
+  if (staged) {
+    for (int32_t k = lane; k < m; k += kWave) ids[w][k] = id_at(id_in, src[s0 + k]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int32_t k0 = 0; k0 < m; k0 += kWave) {
+    const int32_t k = k0 + lane;
+    if (k < m) {
+      const int32_t s = src[s0 + k];
+      const int64_t my = id_at(id_in, s);
+      int32_t rank = 0;
+      if (staged) {
+        for (int32_t q = 0; q < m; ++q) rank += ids[w][q] < my;
+      } else {
+        for (int32_t q = 0; q < m; ++q) rank += id_at(id_in, src[s0 + q]) < my;
+      }
+      const int64_t o = (int64_t)s0 + rank;
+      x_out[3 * o] = x_in[3 * (int64_t)s];
+      x_out[3 * o + 1] = x_in[3 * (int64_t)s + 1];
+      x_out[3 * o + 2] = x_in[3 * (int64_t)s + 2];
+      if (v_in) {
+        v_out[3 * o] = v_in[3 * (int64_t)s];
+        v_out[3 * o + 1] = v_in[3 * (int64_t)s + 1];
+        v_out[3 * o + 2] = v_in[3 * (int64_t)s + 2];
+      }
+      if (type_in) type_out[o] = type_in[s];
+      id_out[o] = my;
+    }
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+size_t bin_workspace(int64_t n, int64_t ncells) {
+  // counts[ncells] + cursor[ncells] + cell[n] + src[n], int32, 256-byte aligned
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return 2 * al((size_t)ncells * 4) + 2 * al((size_t)n * 4);
+}
+
+int launch_bin(const GridK &g, int64_t n, const double *x_in, const double *v_in,
+               const int32_t *type_in, const int64_t *id_in, double *x_out, double *v_out,
+               int32_t *type_out, int64_t *id_out, int32_t *cell_start, void *ws,
+               hipStream_t st) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  char *p = (char *)ws;
+  int32_t *counts = (int32_t *)p;
+  p += al((size_t)g.ncells * 4);
+  int32_t *cursor = (int32_t *)p;
+  p += al((size_t)g.ncells * 4);
+  int32_t *cell = (int32_t *)p;
+  p += al((size_t)n * 4);
+  int32_t *src = (int32_t *)p;
+
+  k_fill_i32<<<blocks_for(g.ncells, 256), 256, 0, st>>>(counts, g.ncells, 0);
+  if (n > 0) k_count<<<blocks_for(n, 256), 256, 0, st>>>(n, x_in, g, cell, counts);
+  k_scan<<<1, kScanThreads, 0, st>>>(g.ncells, counts, cell_start, cursor);
+  if (n > 0) {
+    k_scatter<<<blocks_for(n, 256), 256, 0, st>>>(n, cell, cursor, src);
+    k_permute<<<blocks_for(g.ncells, kPermWaves), kPermWaves * kWave, 0, st>>>(
+        g.ncells, cell_start, src, x_in, v_in, type_in, id_in, x_out, v_out, type_out, id_out);
+  }
+  return check_launch("ljmd_bin");
+}
+
+}  // namespace ljmd

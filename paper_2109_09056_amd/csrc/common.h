@@ -1,0 +1,127 @@
+// Internal helpers shared by the gfx950 kernels of libljmd (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ljmd.h"
+
+namespace ljmd {
+
+constexpr int kWave = 64;
+
+// Box constants handed to kernels by value.
+struct BoxK {
+  double L[3];
+  double invL[3];
+};
+
+// Binning grid: nc cells per dimension, edge h = L/nc.
+struct GridK {
+  int32_t nc[3];
+  double h[3];
+  int32_t ncells;
+};
+
+// Representative of d modulo L nearest zero.  For |d| < L this equals the
+// single shift "d > L/2: d - L; d < -L/2: d + L" bit for bit except when
+// |d| is within rounding of L/2, where both representatives lie at ~L/2,
+// beyond any list cutoff the ABI accepts.
+__device__ __forceinline__ double min_image(double d, double L, double invL) {
+  double k = __builtin_rint(d * invL);
+  return __builtin_fma(-k, L, d);
+}
+
+// r^2 in the fixed order (dx*dx + dy*dy) + dz*dz; the library is compiled
+// with -ffp-contract=off so no FMA is formed here.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Reciprocal by the hardware estimate refined with Newton-Raphson steps
+// y <- y + y (1 - a y), each of which squares the relative error.
+__device__ __forceinline__ double recip64(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-a, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+
+__device__ __forceinline__ float recip32(float a) {
+  float y = __builtin_amdgcn_rcpf(a);
+  float e = __builtin_fmaf(-a, y, 1.0f);
+  return __builtin_fmaf(y, e, y);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    int o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Block of `NW` waves: sums NV values per thread into out[0..NV) for the
+// block, in a fixed order (wave tree, then waves 0..NW-1).  Every thread of
+// the block must call it.  `red` is __shared__ storage of NW*NV doubles.
+template <int NW, int NV>
+__device__ __forceinline__ void block_sum(const double (&v)[NV], double *red, double *out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) red[w * NV + q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// Column sums over `rows` partial rows of `stride` doubles, one block per
+// column q:  out[q] = scale * sum_r p[r*stride + q]  (+= when accumulate),
+// summed in a fixed order.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride,
+                                                   const double *__restrict__ p,
+                                                   double *__restrict__ out, double scale,
+                                                   int accumulate) {
+  __shared__ double red[THREADS / kWave];
+  __shared__ double tot[1];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += THREADS) s += p[r * stride + q];
+  const double v[1] = {s};
+  block_sum<THREADS / kWave, 1>(v, red, tot);
+  if (threadIdx.x == 0) out[q] = accumulate ? out[q] + scale * tot[0] : scale * tot[0];
+}
+
+// Packed upper-triangle index of the type pair (a, b).
+__host__ __device__ __forceinline__ int packed_index(int a, int b, int T) {
+  if (a > b) {
+    int t = a;
+    a = b;
+    b = t;
+  }
+  return a * T - a * (a - 1) / 2 + (b - a);
+}
+
+// ---- host side ----
+int set_error(int code, const char *fmt, ...);
+int check_launch(const char *what);
+BoxK make_box(const ljmd_box *b);
+int make_grid(const ljmd_box *b, double rlist, GridK *g);
+
+}  // namespace ljmd

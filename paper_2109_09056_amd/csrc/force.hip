@@ -1,0 +1,302 @@
+// 12-6 Lennard-Jones forces, per-atom energy, energy and virial over the
+// tiled-ELL neighbor list, gfx950.  Paper: CabanaMD's Lennard-Jones
+// short-range force kernel expressed as a neighbor parallel loop (Cabana
+// "Parallel Loops", "CabanaMD").
+//
+// Pair arithmetic, from u = 4 eps [(sigma/r)^12 - (sigma/r)^6]:
+//   ri2 = 1/r^2, sr6 = (sigma^2 ri2)^3
+//   s   = -u'(r)/r = ri2 sr6 (48 eps sr6 - 24 eps)
+//   u   = sr6 (4 eps sr6 - 4 eps)
+// FP64 form: all of it in FP64 (reciprocal = hardware estimate + two Newton
+// steps).  Mixed form: displacement, r^2 and the cutoff test in FP64 (so the
+// pair set is the FP64 one), then ri2, sr6, s, u and the pair force s*d in
+// FP32, promoted to FP64 for the accumulation of F, e, E and W.
+//
+// FULL list: lane i of the grid owns atom i and walks its row of the tile
+// (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l], one coalesced
+// 256-byte load per wavefront per k); no atomics, fixed summation order, so
+// the result is bitwise reproducible.  HALF list: the owner adds s*d to F_i in
+// registers and subtracts it from F_j with FP64 hardware atomics.
+// Energy and virial: per-block partial sums in a fixed tree order, then one
+// column-sum launch (deterministic).
+#include "common.h"
+
+namespace ljmd {
+
+constexpr int kForceThreads = 256;
+constexpr int kForceWaves = kForceThreads / kWave;
+constexpr int kEvStride = 8;  // partial row: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, pad
+
+struct ForceArgs {
+  BoxK b;
+  double rc2;
+  int32_t ntypes;
+  const double *eps;
+  const double *sig;
+  int32_t n;
+  const double *x;
+  const int32_t *type;
+  const int32_t *nbr;
+  const int32_t *nnbr;
+  int32_t maxn;
+  double *F;
+  double *e_atom;
+  double *partial;
+};
+
+namespace {
+
+// Coefficients of one type pair: sigma^2, 48 eps, 24 eps, 4 eps.
+struct Coef {
+  double sig2, c12, c6, e4;
+};
+
+__device__ __forceinline__ Coef coef_of(const double *eps, const double *sig, int p) {
+  Coef c;
+  const double e = eps[p], s = sig[p];
+  c.sig2 = s * s;
+  c.c12 = 48.0 * e;
+  c.c6 = 24.0 * e;
+  c.e4 = 4.0 * e;
+  return c;
+}
+
+// Full T x T table in LDS (T > 1): entry (a, b) at 4*(a*T + b).
+__device__ __forceinline__ void load_table(const ForceArgs &a, double *tab) {
+  const int T = a.ntypes;
+  for (int q = threadIdx.x; q < T * T; q += blockDim.x) {
+    const Coef c = coef_of(a.eps, a.sig, packed_index(q / T, q % T, T));
+    tab[4 * q] = c.sig2;
+    tab[4 * q + 1] = c.c12;
+    tab[4 * q + 2] = c.c6;
+    tab[4 * q + 3] = c.e4;
+  }
+  __syncthreads();
+}
+
+struct PairOut {
+  double fx, fy, fz, u;
+};
+
+// Pair force components s*d and energy u for r2 < rc2.
+template <bool MIXED, bool EV>
+__device__ __forceinline__ PairOut lj_pair(double dx, double dy, double dz, double r2,
+                                           const Coef &c) {
+  PairOut o;
+  if constexpr (MIXED) {
+    const float ri2 = recip32((float)r2);
+    const float sr2 = (float)c.sig2 * ri2;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float s = ri2 * sr6 * __builtin_fmaf((float)c.c12, sr6, -(float)c.c6);
+    o.fx = (double)(s * (float)dx);
+    o.fy = (double)(s * (float)dy);
+    o.fz = (double)(s * (float)dz);
+    if constexpr (EV) o.u = (double)(sr6 * __builtin_fmaf((float)c.e4, sr6, -(float)c.e4));
+  } else {
+    const double ri2 = recip64(r2);
+    const double sr2 = c.sig2 * ri2;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double s = ri2 * sr6 * __builtin_fma(c.c12, sr6, -c.c6);
+    o.fx = s * dx;
+    o.fy = s * dy;
+    o.fz = s * dz;
+    if constexpr (EV) o.u = sr6 * __builtin_fma(c.e4, sr6, -c.e4);
+  }
+  return o;
+}
+
+template <bool MIXED, bool T1, bool EV>
+__global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
+  __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
+  __shared__ double red[kForceWaves * 7];
+  Coef c1;
+  if constexpr (T1) {
+    c1 = coef_of(a.eps, a.sig, 0);
+  } else {
+    load_table(a, tab);
+  }
+  const int32_t i = blockIdx.x * kForceThreads + threadIdx.x;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+  if (i < a.n) {
+    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
+                 zi = a.x[3 * (int64_t)i + 2];
+    const int ti = T1 ? 0 : a.type[i];
+    const int32_t cnt = a.nnbr[i];
+    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
+    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
+    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
+    for (int32_t k = 0; k < cnt; ++k) {
+      const int32_t j = row[(int64_t)k * kWave];
+      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
+      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
+      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
+      const double r2 = dist2(dx, dy, dz);
+      if (r2 < a.rc2) {
+        Coef c;
+        if constexpr (T1) {
+          c = c1;
+        } else {
+          const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
+          c = Coef{t[0], t[1], t[2], t[3]};
+        }
+        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
+        fx += p.fx;
+        fy += p.fy;
+        fz += p.fz;
+        if constexpr (EV) {
+          e += p.u;
+          wxx = __builtin_fma(dx, p.fx, wxx);
+          wyy = __builtin_fma(dy, p.fy, wyy);
+          wzz = __builtin_fma(dz, p.fz, wzz);
+          wxy = __builtin_fma(dx, p.fy, wxy);
+          wxz = __builtin_fma(dx, p.fz, wxz);
+          wyz = __builtin_fma(dy, p.fz, wyz);
+        }
+      }
+    }
+    a.F[3 * (int64_t)i] = fx;
+    a.F[3 * (int64_t)i + 1] = fy;
+    a.F[3 * (int64_t)i + 2] = fz;
+    if (a.e_atom) a.e_atom[i] = 0.5 * e;
+  }
+  if constexpr (EV) {
+    const double v[7] = {0.5 * e, 0.5 * wxx, 0.5 * wyy, 0.5 * wzz, 0.5 * wxy, 0.5 * wxz, 0.5 * wyz};
+    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+  }
+}
+
+__global__ void k_zero_f64(double *p, int64_t m) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) p[q] = 0.0;
+}
+
+template <bool MIXED, bool T1, bool EV>
+__global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
+  __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
+  __shared__ double red[kForceWaves * 7];
+  Coef c1;
+  if constexpr (T1) {
+    c1 = coef_of(a.eps, a.sig, 0);
+  } else {
+    load_table(a, tab);
+  }
+  const int32_t i = blockIdx.x * kForceThreads + threadIdx.x;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+  if (i < a.n) {
+    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
+                 zi = a.x[3 * (int64_t)i + 2];
+    const int ti = T1 ? 0 : a.type[i];
+    const int32_t cnt = a.nnbr[i];
+    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
+    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
+    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
+    for (int32_t k = 0; k < cnt; ++k) {
+      const int32_t j = row[(int64_t)k * kWave];
+      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
+      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
+      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
+      const double r2 = dist2(dx, dy, dz);
+      if (r2 < a.rc2) {
+        Coef c;
+        if constexpr (T1) {
+          c = c1;
+        } else {
+          const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
+          c = Coef{t[0], t[1], t[2], t[3]};
+        }
+        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
+        fx += p.fx;
+        fy += p.fy;
+        fz += p.fz;
+        unsafeAtomicAdd(&a.F[3 * (int64_t)j], -p.fx);
+        unsafeAtomicAdd(&a.F[3 * (int64_t)j + 1], -p.fy);
+        unsafeAtomicAdd(&a.F[3 * (int64_t)j + 2], -p.fz);
+        if constexpr (EV) {
+          e += p.u;
+          if (a.e_atom) unsafeAtomicAdd(&a.e_atom[j], 0.5 * p.u);
+          wxx = __builtin_fma(dx, p.fx, wxx);
+          wyy = __builtin_fma(dy, p.fy, wyy);
+          wzz = __builtin_fma(dz, p.fz, wzz);
+          wxy = __builtin_fma(dx, p.fy, wxy);
+          wxz = __builtin_fma(dx, p.fz, wxz);
+          wyz = __builtin_fma(dy, p.fz, wyz);
+        }
+      }
+    }
+    unsafeAtomicAdd(&a.F[3 * (int64_t)i], fx);
+    unsafeAtomicAdd(&a.F[3 * (int64_t)i + 1], fy);
+    unsafeAtomicAdd(&a.F[3 * (int64_t)i + 2], fz);
+    if (EV && a.e_atom) unsafeAtomicAdd(&a.e_atom[i], 0.5 * e);
+  }
+  if constexpr (EV) {
+    const double v[7] = {e, wxx, wyy, wzz, wxy, wxz, wyz};
+    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+  }
+}
+
+template <bool MIXED, bool T1, bool EV>
+void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
+  if (kind == LJMD_HALF)
+    k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
+  else
+    k_force_full<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
+}
+
+template <bool MIXED>
+void launch_prec(const ForceArgs &a, int kind, bool ev, unsigned nblk, hipStream_t st) {
+  const bool t1 = a.ntypes == 1;
+  if (t1 && ev) launch_one<MIXED, true, true>(a, kind, nblk, st);
+  else if (t1) launch_one<MIXED, true, false>(a, kind, nblk, st);
+  else if (ev) launch_one<MIXED, false, true>(a, kind, nblk, st);
+  else launch_one<MIXED, false, false>(a, kind, nblk, st);
+}
+
+}  // namespace
+
+unsigned force_blocks(int64_t n) {
+  const int64_t b = (n + kForceThreads - 1) / kForceThreads;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+size_t force_workspace(int64_t n) { return (size_t)force_blocks(n) * kEvStride * sizeof(double); }
+
+int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t ntypes,
+                  const double *eps, const double *sig, int64_t n, const double *x,
+                  const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                  double *F, double *e_atom, double *ev, void *ws, hipStream_t st) {
+  ForceArgs a;
+  a.b = b;
+  a.rc2 = rc * rc;
+  a.ntypes = ntypes;
+  a.eps = eps;
+  a.sig = sig;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.type = type;
+  a.nbr = nbr;
+  a.nnbr = nnbr;
+  a.maxn = maxn;
+  a.F = F;
+  a.e_atom = e_atom;
+  a.partial = (double *)ws;
+  const unsigned nblk = force_blocks(n);
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  if (kind == LJMD_HALF) {
+    k_zero_f64<<<(unsigned)((3 * n + 255) / 256 + 1), 256, 0, st>>>(F, 3 * n);
+    if (e_atom) k_zero_f64<<<(unsigned)((n + 255) / 256 + 1), 256, 0, st>>>(e_atom, n);
+  }
+  if (n > 0) {
+    if (precision == LJMD_MIXED)
+      launch_prec<true>(a, kind, want_ev, nblk, st);
+    else
+      launch_prec<false>(a, kind, want_ev, nblk, st);
+  } else if (ev) {
+    k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
+  }
+  if (ev) k_colsum<256><<<7, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, a.partial, ev, 1.0, 0);
+  return check_launch("ljmd_compute_forces");
+}
+
+}  // namespace ljmd

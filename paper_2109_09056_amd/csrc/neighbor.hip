@@ -1,0 +1,191 @@
+// Verlet neighbor lists over the 27-cell stencil, gfx950.  Paper: Cabana
+// "Neighbor List Creation" (distance-criterion lists built by binning, dense
+// storage, thread-parallel creation).
+//
+// One wavefront per home cell.  The candidates -- every atom of the stencil
+// cells (offsets -1, 0, +1 per dimension modulo nc, with repeats removed when
+// nc < 3) -- are loaded once into registers, 64 per register slot (lane t of
+// slot r holds candidate 64 r + t).  The wavefront then walks the home atoms
+// one at a time: every lane tests its candidates against the (uniform) home
+// atom, a ballot + mbcnt prefix compacts the hits, and each hit is stored in
+// the home atom's row of the tiled-ELL list:
+//   nbr[((i / 64) * maxn + k) * 64 + (i % 64)].
+// Cells with more candidates than the register slots hold fall back to
+// reading candidates from global memory per home atom.
+#include "common.h"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kSlots = 12;  // register slots: up to 768 candidates staged
+
+__global__ void k_fill_scalar(int32_t *p, int32_t val) { *p = val; }
+
+// Stencil of cell c: its candidate ranges [rs[s], rs[s] + len) in sorted order
+// and the prefix pre[s] of their lengths.  Returns the number of ranges.
+__device__ __forceinline__ int stencil_ranges(const GridK &g, int32_t c, const int32_t *cell_start,
+                                              int32_t *rs, int32_t *pre) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t cc[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+  int32_t cells[3][3];
+  int cnt[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int32_t m = g.nc[k];
+    if (m >= 3) {
+      cells[k][0] = cc[k] == 0 ? m - 1 : cc[k] - 1;
+      cells[k][1] = cc[k];
+      cells[k][2] = cc[k] == m - 1 ? 0 : cc[k] + 1;
+      cnt[k] = 3;
+    } else {
+      cells[k][0] = 0;
+      cells[k][1] = 1;
+      cells[k][2] = 0;
+      cnt[k] = m;
+    }
+  }
+  const int S = cnt[0] * cnt[1] * cnt[2];
+  int32_t len = 0;
+  if (lane < S) {
+    const int ix = lane % cnt[0];
+    const int iy = (lane / cnt[0]) % cnt[1];
+    const int iz = lane / (cnt[0] * cnt[1]);
+    const int32_t s = (cells[2][iz] * g.nc[1] + cells[1][iy]) * g.nc[0] + cells[0][ix];
+    const int32_t a = cell_start[s];
+    rs[lane] = a;
+    len = cell_start[s + 1] - a;
+  }
+  // inclusive prefix of len over the first S lanes (S <= 27 < 32)
+  int32_t inc = len;
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    int32_t o = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += o;
+  }
+  if (lane < S) pre[lane + 1] = inc;
+  if (lane == 0) pre[0] = 0;
+  __syncthreads();  // the block is this one wavefront
+  return S;
+}
+
+// Sorted index of candidate t (t < pre[S]).
+__device__ __forceinline__ int32_t locate(int32_t t, const int32_t *rs, const int32_t *pre) {
+  int r = 0;
+  while (t >= pre[r + 1]) ++r;
+  return rs[r] + (t - pre[r]);
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
+                                                 const double *__restrict__ x,
+                                                 const int32_t *__restrict__ cell_start,
+                                                 int32_t maxn, int32_t *__restrict__ nbr,
+                                                 int32_t *__restrict__ nnbr,
+                                                 int32_t *__restrict__ max_count) {
+  __shared__ int32_t rs[27];
+  __shared__ int32_t pre[28];
+  const int lane = threadIdx.x;
+  const int32_t c = blockIdx.x;
+  const int32_t h0 = cell_start[c];
+  const int32_t h1 = cell_start[c + 1];
+  if (h0 == h1) return;
+  const int S = stencil_ranges(g, c, cell_start, rs, pre);
+  const int32_t total = pre[S];
+  const int nslot = (total + kWave - 1) / kWave;
+  const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
+  const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
+  int32_t maxc = 0;
+
+  if (nslot <= kSlots) {
+    double qx[kSlots], qy[kSlots], qz[kSlots];
+    int32_t qj[kSlots];
+#pragma unroll
+    for (int r = 0; r < kSlots; ++r) {
+      const int32_t t = r * kWave + lane;
+      qj[r] = -1;
+      qx[r] = qy[r] = qz[r] = 0.0;
+      if (r < nslot && t < total) {
+        const int32_t j = locate(t, rs, pre);
+        qj[r] = j;
+        qx[r] = x[3 * (int64_t)j];
+        qy[r] = x[3 * (int64_t)j + 1];
+        qz[r] = x[3 * (int64_t)j + 2];
+      }
+    }
+    for (int32_t i = h0; i < h1; ++i) {
+      const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
+      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      int32_t base = 0;
+#pragma unroll
+      for (int r = 0; r < kSlots; ++r) {
+        if (r < nslot) {
+          const double dx = min_image(xi - qx[r], L0, iL0);
+          const double dy = min_image(yi - qy[r], L1, iL1);
+          const double dz = min_image(zi - qz[r], L2, iL2);
+          const double r2 = dist2(dx, dy, dz);
+          const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
+          const uint64_t m = __ballot(ok);
+          if (ok) {
+            const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                                         (uint32_t)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (k < maxn) row[(int64_t)k * kWave] = qj[r];
+          }
+          base += (int32_t)__popcll(m);
+        }
+      }
+      if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
+      maxc = base > maxc ? base : maxc;
+    }
+  } else {
+    for (int32_t i = h0; i < h1; ++i) {
+      const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
+      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      int32_t base = 0;
+      for (int r = 0; r < nslot; ++r) {
+        const int32_t t = r * kWave + lane;
+        bool ok = false;
+        int32_t j = -1;
+        if (t < total) {
+          j = locate(t, rs, pre);
+          const double dx = min_image(xi - x[3 * (int64_t)j], L0, iL0);
+          const double dy = min_image(yi - x[3 * (int64_t)j + 1], L1, iL1);
+          const double dz = min_image(zi - x[3 * (int64_t)j + 2], L2, iL2);
+          ok = dist2(dx, dy, dz) < rl2 && (HALF ? j > i : j != i);
+        }
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+          const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                                       (uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (k < maxn) row[(int64_t)k * kWave] = j;
+        }
+        base += (int32_t)__popcll(m);
+      }
+      if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
+      maxc = base > maxc ? base : maxc;
+    }
+  }
+  if (lane == 0) atomicMax(max_count, maxc);
+}
+
+}  // namespace
+
+int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n, const double *x,
+                 const int32_t *cell_start, int32_t maxn, int32_t *nbr, int32_t *nnbr,
+                 int32_t *max_count, hipStream_t st) {
+  k_fill_scalar<<<1, 1, 0, st>>>(max_count, 0);
+  if (n > 0) {
+    const double rl2 = rlist * rlist;
+    if (kind == LJMD_HALF)
+      k_build<true><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn, nbr, nnbr,
+                                               max_count);
+    else
+      k_build<false><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn, nbr, nnbr,
+                                                max_count);
+  }
+  return check_launch("ljmd_build_neighbors");
+}
+
+}  // namespace ljmd

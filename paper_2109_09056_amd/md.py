@@ -1,0 +1,187 @@
+"""Short-range LJ molecular dynamics on one MI355X: the timestep loop.
+
+The step follows the paper's timestep anatomy for short-range MD
+(Introduction): from the neighbor list, compute each particle's forces,
+propagate, and re-sort; with CabanaMD's split (CabanaMD subsection) the
+library side sorts and builds lists while the force kernel and the
+integration are the application's.  Every arithmetic step runs in libljmd's
+HIP kernels; this module only owns buffers, the rebuild cadence and the
+neighbor-capacity check.
+
+Velocity Verlet with a fixed rebuild cadence (no displacement check):
+    v += dt/2 F/m; x += dt v; wrap            (ljmd_integrate KICK_DRIFT)
+    every `rebuild_every` steps: re-sort by cell and rebuild the list
+    F = F(x)                                   (ljmd_compute_forces)
+    v += dt/2 F/m                              (ljmd_integrate KICK)
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import ops
+from ._lib import FP64, FULL, HALF, KICK, KICK_DRIFT
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+def _to(t, dtype, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+def initial_maxn(n, L, rlist, kind):
+    """Row capacity guess from the mean density: 1.3x the ideal-gas count plus 16."""
+    vol = float(L[0]) * float(L[1]) * float(L[2])
+    mean = 4.0 / 3.0 * math.pi * rlist ** 3 * n / vol
+    if kind == HALF:
+        mean *= 0.5
+    return int(math.ceil((1.3 * mean + 16) / 4.0) * 4)
+
+
+class NeighborList:
+    """Atoms sorted by cell plus their tiled-ELL Verlet list (library-owned indexing)."""
+
+    def __init__(self, L, rlist, kind=FULL, maxn=None, device=None):
+        self.L = [float(v) for v in L]
+        self.rlist = float(rlist)
+        self.kind = kind
+        self.device = _dev(device)
+        self.maxn = maxn
+        self.nbr = self.nnbr = self.cell_start = None
+        self.max_count = None
+        self.builds = 0
+        self.overflows = 0
+
+    def build(self, x_sorted, cell_start):
+        """Build from cell-sorted positions; grow the row capacity until nothing is cut."""
+        n = x_sorted.shape[0]
+        if self.maxn is None:
+            self.maxn = initial_maxn(n, self.L, self.rlist, self.kind)
+        while True:
+            self.nbr, self.nnbr, self.max_count = ops.build_neighbors(
+                self.L, self.rlist, self.kind, x_sorted, cell_start, self.maxn, self.nbr,
+                self.nnbr if self.nnbr is not None and self.nnbr.numel() == n else None,
+                self.max_count)
+            need = int(self.max_count.item())
+            if need <= self.maxn:
+                break
+            self.overflows += 1
+            self.maxn = int(math.ceil((need + 8) / 4.0) * 4)
+            self.nbr = None
+        self.cell_start = cell_start
+        self.builds += 1
+        return self
+
+
+class LJSim:
+    """Velocity-Verlet NVE simulation of a (multi-type) 12-6 LJ system on one GPU.
+
+    State arrays live on the device in cell-sorted order; `ids` maps sorted
+    position k to the caller's atom ids[k].
+    """
+
+    def __init__(self, L, rc=2.5, skin=0.3, eps=(1.0,), sigma=(1.0,), precision=FP64, kind=FULL,
+                 dt=0.005, mass=1.0, rebuild_every=20, device=None):
+        self.device = _dev(device)
+        self.L = [float(v) for v in (L if hasattr(L, "__len__") else (L, L, L))]
+        self.rc = float(rc)
+        self.rlist = float(rc) + float(skin)
+        self.eps = _to(eps, torch.float64, self.device).reshape(-1)
+        self.sigma = _to(sigma, torch.float64, self.device).reshape(-1)
+        self.precision = precision
+        self.kind = kind
+        self.dt = float(dt)
+        self.mass = float(mass)
+        self.rebuild_every = int(rebuild_every)
+        self.nl = NeighborList(self.L, self.rlist, kind, device=self.device)
+        self.step_count = 0
+        self._ws = {}
+
+    # ------------------------------------------------------------------ setup
+    def load(self, x, v, types=None, ids=None):
+        dev = self.device
+        x = _to(x, torch.float64, dev)
+        n = x.shape[0]
+        self.n = n
+        v = _to(v, torch.float64, dev) if v is not None else torch.zeros_like(x)
+        types = (_to(types, torch.int32, dev) if types is not None
+                 else torch.zeros(n, dtype=torch.int32, device=dev))
+        ids = _to(ids, torch.int64, dev) if ids is not None else None
+        self.x, self.v, self.types, self.ids = x, v, types, ids
+        # ping-pong buffers for the re-sort
+        self._alt = (torch.empty_like(x), torch.empty_like(v), torch.empty_like(types),
+                     torch.empty(n, dtype=torch.int64, device=dev))
+        self.F = torch.empty_like(x)
+        self.e_atom = torch.empty(n, dtype=torch.float64, device=dev)
+        self.ev = torch.zeros(7, dtype=torch.float64, device=dev)
+        self.ke = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.cell_start = None
+        for op in (ops.OP_FORCES, ops.OP_INTEGRATE):
+            self._ws[op] = torch.empty(max(ops.workspace_bytes(op, n), 8), dtype=torch.uint8,
+                                       device=dev)
+        self.rebuild()
+        self.compute_forces(energy=True)
+        return self
+
+    def rebuild(self):
+        xo, vo, to, io, self.cell_start = ops.bin(
+            self.L, self.rlist, self.x, self.v, self.types, self.ids, out=self._alt,
+            cell_start=self.cell_start, ws=self._ws.get(ops.OP_BIN))
+        self._alt = (self.x, self.v, self.types,
+                     self.ids if self.ids is not None else torch.empty_like(io))
+        self.x, self.v, self.types, self.ids = xo, vo, to, io
+        self.nl.build(self.x, self.cell_start)
+
+    # ------------------------------------------------------------------- step
+    def compute_forces(self, energy=True):
+        ops.compute_forces(self.L, self.precision, self.kind, self.rc, self.eps, self.sigma,
+                           self.x, self.types, self.nl.nbr, self.nl.nnbr, self.nl.maxn, F=self.F,
+                           e_atom=self.e_atom if energy else None,
+                           ev=self.ev if energy else None, want_energy=energy,
+                           ws=self._ws[ops.OP_FORCES])
+
+    def step(self, nsteps=1, energy=True, force_timer=None):
+        """Advance nsteps velocity-Verlet steps; energy: E, W and KE every step.
+
+        force_timer: optional list receiving (start, end) timing events recorded on the
+        current stream around every force call.
+        """
+        for _ in range(nsteps):
+            ops.integrate(KICK_DRIFT, self.dt, self.mass, self.L, self.x, self.v, self.F)
+            self.step_count += 1
+            if self.step_count % self.rebuild_every == 0:
+                self.rebuild()
+            if force_timer is not None:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                self.compute_forces(energy)
+                b.record()
+                force_timer.append((a, b))
+            else:
+                self.compute_forces(energy)
+            ops.integrate(KICK, self.dt, self.mass, self.L, self.x, self.v, self.F,
+                          ke=self.ke if energy else None, ws=self._ws[ops.OP_INTEGRATE])
+        return self
+
+    # ---------------------------------------------------------------- reports
+    def thermo(self):
+        ev = self.ev.cpu()
+        ke = float(self.ke.cpu()[0])
+        pe = float(ev[0])
+        vol = self.L[0] * self.L[1] * self.L[2]
+        temp = 2.0 * ke / (3 * self.n - 3)
+        press = (self.n * temp + float(ev[1] + ev[2] + ev[3]) / 3.0) / vol
+        return dict(step=self.step_count, pe=pe, ke=ke, etot=pe + ke, temp=temp, press=press,
+                    virial=ev[1:].tolist(), builds=self.nl.builds, maxn=self.nl.maxn)
+
+    def in_caller_order(self, t):
+        """Rows of a sorted-order tensor rearranged into the caller's atom order (ids)."""
+        return ops.scatter_rows(self.ids, t.contiguous())

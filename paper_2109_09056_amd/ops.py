@@ -1,0 +1,268 @@
+"""Python face of the libljmd C ABI: one function per entry point, same names.
+
+Argument marshalling only: tensors must already live on the GPU with the
+dtype and layout the ABI states; each call passes their device pointers and
+the current torch stream to the library, which does every step in its own
+HIP kernels.  PyTorch supplies device memory (including workspaces) and the
+stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
+                   MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_FORCES, OP_INTEGRATE, OP_LOSS,
+                   TILE, LjmdError, make_box)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t, name, dtype, shape=None, device=None):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _ws(op, n, device, ncells=0, ntypes=1, ws=None):
+    need = int(_lib.load().ljmd_workspace_bytes(op, n, ncells, ntypes))
+    if ws is not None and ws.numel() >= need:
+        return ws, need
+    return torch.empty(max(need, 8), dtype=torch.uint8, device=device), need
+
+
+def grid(L, rlist):
+    """Cell counts per dimension for binning at rlist (host computation)."""
+    nc = (ctypes.c_int32 * 3)()
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_grid(ctypes.byref(b), float(rlist), nc), "ljmd_grid")
+    return (int(nc[0]), int(nc[1]), int(nc[2]))
+
+
+def workspace_bytes(op, n, ncells=0, ntypes=1) -> int:
+    return int(_lib.load().ljmd_workspace_bytes(op, n, ncells, ntypes))
+
+
+def bin(L, rlist, x, v=None, types=None, ids=None, out=None, cell_start=None, ws=None):
+    """Counting sort into cells.  Returns (x, v, types, ids, cell_start) in sorted order."""
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(v, "v", torch.float64, (n, 3), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(ids, "ids", torch.int64, (n,), dev)
+    nc = grid(L, rlist)
+    ncells = nc[0] * nc[1] * nc[2]
+    if out is None:
+        out = (torch.empty_like(x), None if v is None else torch.empty_like(v),
+               None if types is None else torch.empty_like(types),
+               torch.empty(n, dtype=torch.int64, device=dev))
+    xo, vo, to, io = out
+    if cell_start is None or cell_start.numel() < ncells + 1:
+        cell_start = torch.empty(ncells + 1, dtype=torch.int32, device=dev)
+    _need(cell_start, "cell_start", torch.int32, None, dev)
+    ws, need = _ws(OP_BIN, n, dev, ncells=ncells, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_bin(
+        ctypes.byref(b), float(rlist), n, _ptr(x), _ptr(v), _ptr(types), _ptr(ids), _ptr(xo),
+        _ptr(vo), _ptr(to), _ptr(io), _ptr(cell_start), cell_start.numel(), _ptr(ws), need,
+        _stream(dev)), "ljmd_bin")
+    return xo, vo, to, io, cell_start
+
+
+def list_shape(n, maxn):
+    tiles = (n + TILE - 1) // TILE
+    return (max(tiles, 1) * maxn * TILE,)
+
+
+def build_neighbors(L, rlist, kind, x, cell_start, maxn, nbr=None, nnbr=None, max_count=None):
+    """Tiled-ELL Verlet list.  Returns (nbr, nnbr, max_count) -- max_count is a device scalar."""
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(cell_start, "cell_start", torch.int32, None, dev)
+    if nbr is None or nbr.numel() < list_shape(n, maxn)[0]:
+        nbr = torch.empty(list_shape(n, maxn), dtype=torch.int32, device=dev)
+    if nnbr is None:
+        nnbr = torch.empty(n, dtype=torch.int32, device=dev)
+    if max_count is None:
+        max_count = torch.empty(1, dtype=torch.int32, device=dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    _need(max_count, "max_count", torch.int32, (1,), dev)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_build_neighbors(
+        ctypes.byref(b), float(rlist), int(kind), n, _ptr(x), _ptr(cell_start), int(maxn),
+        _ptr(nbr), _ptr(nnbr), _ptr(max_count), _stream(dev)), "ljmd_build_neighbors")
+    return nbr, nnbr, max_count
+
+
+def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn, F=None,
+                   e_atom=None, ev=None, want_energy=True, ws=None):
+    """Forces (and per-atom energy / [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] when wanted)."""
+    n = x.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (n, 3))
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if F is None:
+        F = torch.empty_like(x)
+    if want_energy:
+        if e_atom is None:
+            e_atom = torch.empty(n, dtype=torch.float64, device=dev)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_atom, "e_atom", torch.float64, (n,), dev)
+    _need(ev, "ev", torch.float64, (7,), dev)
+    ws, need = _ws(OP_FORCES, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_compute_forces(
+        ctypes.byref(b), int(precision), int(kind), float(rc), ntypes, _ptr(eps), _ptr(sigma), n,
+        _ptr(x), _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(F), _ptr(e_atom), _ptr(ev),
+        _ptr(ws), need, _stream(dev)), "ljmd_compute_forces")
+    return F, e_atom, ev
+
+
+def integrate(stage, dt, mass, L, x, v, F, ke=None, ws=None):
+    """In-place velocity-Verlet stage; ke (device scalar) receives 1/2 m sum v^2 if given."""
+    n = v.shape[0]
+    dev = v.device
+    _need(v, "v", torch.float64, (n, 3))
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(x, "x", torch.float64, (n, 3), dev)
+    _need(ke, "ke", torch.float64, (1,), dev)
+    need = 0
+    if ke is not None:
+        ws, need = _ws(OP_INTEGRATE, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_integrate(
+        int(stage), float(dt), float(mass), ctypes.byref(b), n, _ptr(x), _ptr(v), _ptr(F),
+        _ptr(ke), _ptr(ws) if ke is not None else None, need, _stream(dev)), "ljmd_integrate")
+
+
+def force_backward(L, precision, rc, eps, sigma, x, types, nbr, nnbr, maxn, g, gx=None,
+                   geps=None, gsigma=None, accumulate=False, ws=None):
+    """(gx, geps, gsigma) = VJP of the forces with cotangent g (FULL list)."""
+    n = x.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (n, 3))
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    _need(g, "g", torch.float64, (n, 3), dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if gx is None:
+        gx = torch.empty_like(x)
+    if geps is None:
+        geps = torch.empty_like(eps)
+    if gsigma is None:
+        gsigma = torch.empty_like(eps)
+    _need(gx, "gx", torch.float64, (n, 3), dev)
+    _need(geps, "geps", torch.float64, tuple(eps.shape), dev)
+    _need(gsigma, "gsigma", torch.float64, tuple(eps.shape), dev)
+    ws, need = _ws(OP_BACKWARD, n, dev, ntypes=ntypes, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_force_backward(
+        ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, _ptr(x),
+        _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(g), _ptr(gx), _ptr(geps),
+        _ptr(gsigma), 1 if accumulate else 0, _ptr(ws), need, _stream(dev)),
+        "ljmd_force_backward")
+    return gx, geps, gsigma
+
+
+def adjoint_kick(dt, w, xbar, vbar, g):
+    n = xbar.shape[0]
+    dev = xbar.device
+    for t, name in ((xbar, "xbar"), (vbar, "vbar"), (g, "g")):
+        _need(t, name, torch.float64, (n, 3), dev)
+    _lib.check(_lib.load().ljmd_adjoint_kick(n, float(dt), float(w), _ptr(xbar), _ptr(vbar),
+                                             _ptr(g), _stream(dev)), "ljmd_adjoint_kick")
+
+
+def traj_loss(L, x, xref, xbar=None, loss=None, ws=None):
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(xref, "xref", torch.float64, (n, 3), dev)
+    if xbar is None:
+        xbar = torch.empty_like(x)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+    _need(xbar, "xbar", torch.float64, (n, 3), dev)
+    _need(loss, "loss", torch.float64, (1,), dev)
+    ws, need = _ws(OP_LOSS, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_traj_loss(ctypes.byref(b), n, _ptr(x), _ptr(xref), _ptr(xbar),
+                                          _ptr(loss), _ptr(ws), need, _stream(dev)),
+               "ljmd_traj_loss")
+    return loss, xbar
+
+
+def scatter_rows(ids, src, dst=None):
+    """dst[ids[k]] = src[k] (rows); maps sorted-order results back to the caller's order."""
+    n = src.shape[0]
+    dev = src.device
+    width = 1 if src.dim() == 1 else int(src.shape[1])
+    _need(ids, "ids", torch.int64, (n,), dev)
+    _need(src, "src", torch.float64, tuple(src.shape), dev)
+    if dst is None:
+        dst = torch.empty_like(src)
+    _need(dst, "dst", torch.float64, tuple(src.shape), dev)
+    _lib.check(_lib.load().ljmd_scatter_rows(n, width, _ptr(ids), _ptr(src), _ptr(dst),
+                                             _stream(dev)), "ljmd_scatter_rows")
+    return dst
+
+
+def gather_rows(ids, src, dst=None):
+    """dst[k] = src[ids[k]] (rows); brings caller-order data into sorted order."""
+    n = ids.shape[0]
+    dev = src.device
+    width = 1 if src.dim() == 1 else int(src.shape[1])
+    _need(ids, "ids", torch.int64, (n,), dev)
+    _need(src, "src", torch.float64, None, dev)
+    if src.shape[0] != n:
+        raise ValueError("src must have one row per id")
+    if dst is None:
+        dst = torch.empty_like(src)
+    _need(dst, "dst", torch.float64, tuple(src.shape), dev)
+    _lib.check(_lib.load().ljmd_gather_rows(n, width, _ptr(ids), _ptr(src), _ptr(dst),
+                                            _stream(dev)), "ljmd_gather_rows")
+    return dst
+
+
+def _ntypes(eps) -> int:
+    p = int(eps.numel())
+    t = int(round(((8 * p + 1) ** 0.5 - 1) / 2))
+    if t * (t + 1) // 2 != p or not 1 <= t <= MAX_TYPES:
+        raise ValueError(f"packed parameter length {p} is not T(T+1)/2 with 1 <= T <= {MAX_TYPES}")
+    return t

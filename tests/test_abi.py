@@ -1,0 +1,137 @@
+"""The C-ABI library loads on the CPU host, exports every symbol its header
+declares, and rejects bad arguments on the host before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from helpers import header_symbols
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2109_09056_amd import _lib
+    return _lib
+
+
+def test_exports_every_header_symbol(lib):
+    L = lib.load()
+    syms = header_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(lib.SIGNATURES) == syms
+
+
+def test_constants_match_header(lib):
+    import re
+    from helpers import ROOT
+    hdr = open(f"{ROOT}/include/ljmd.h").read()
+    consts = dict(re.findall(r"#define (LJMD_\w+) (\d+)", hdr))
+    for name, val in consts.items():
+        short = name[len("LJMD_"):]
+        if hasattr(lib, short):
+            assert getattr(lib, short) == int(val), name
+
+
+def test_grid_matches_oracle_rule(lib, orc):
+    for L, rl in [((6.718385,) * 3, 2.8), ((33.59,) * 3, 2.8), ((83.98,) * 3, 2.8),
+                  ((5.8, 7.1, 19.3), 2.8), ((15.980117845432297, 26.507607108814266, 27.5), 2.8)]:
+        nc = (ctypes.c_int32 * 3)()
+        b = lib.make_box(L)
+        assert lib.load().ljmd_grid(ctypes.byref(b), rl, nc) == 0
+        assert list(nc) == list(orc.grid(L, rl))
+
+
+def test_workspace_sizes(lib):
+    W = lib.load().ljmd_workspace_bytes
+    assert W(lib.OP_BIN, 1000, 100, 1) >= 4 * (2 * 100 + 2 * 1000)
+    assert W(lib.OP_FORCES, 500000, 0, 1) >= 8 * 7 * (500000 // 256)
+    assert W(lib.OP_BACKWARD, 1000, 0, 2) >= W(lib.OP_BACKWARD, 1000, 0, 1)
+    assert W(99, 10, 10, 1) == 0
+
+
+def test_error_strings(lib):
+    L = lib.load()
+    for code in range(5):
+        assert L.ljmd_error_string(code)
+    assert b"unknown" in L.ljmd_error_string(42)
+
+
+def call(lib, name, *args):
+    return getattr(lib.load(), name)(*args)
+
+
+def test_validation_rejects_bad_arguments(lib):
+    b = lib.make_box((10.0, 10.0, 10.0))
+    bb = ctypes.byref(b)
+    nc = (ctypes.c_int32 * 3)()
+    assert call(lib, "ljmd_grid", None, 2.8, nc) == lib.EINVAL
+    assert call(lib, "ljmd_grid", bb, 5.0, nc) == lib.EBOX  # rlist >= L/2
+    assert call(lib, "ljmd_grid", bb, -1.0, nc) == lib.EINVAL
+    bad = lib.make_box((10.0, -1.0, 10.0))
+    assert call(lib, "ljmd_grid", ctypes.byref(bad), 2.8, nc) == lib.EBOX
+    assert b"L[1]" in lib.load().ljmd_last_error()
+    nanb = lib.make_box((10.0, float("nan"), 10.0))
+    assert call(lib, "ljmd_grid", ctypes.byref(nanb), 2.8, nc) == lib.EBOX
+    # bin: negative n, missing cell buffer, too-small cell buffer, missing workspace
+    fake = ctypes.c_void_p(16)
+    assert call(lib, "ljmd_bin", bb, 2.8, -5, *([fake] * 8), fake, 100, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_bin", bb, 2.8, 10, *([fake] * 8), None, 100, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_bin", bb, 2.8, 10, *([fake] * 8), fake, 5, fake, 1 << 20,
+                None) == lib.EWORKSPACE
+    assert call(lib, "ljmd_bin", bb, 2.8, 10, *([fake] * 8), fake, 100, None, 0,
+                None) == lib.EWORKSPACE
+    # build: bad kind, bad maxn, rlist too large
+    assert call(lib, "ljmd_build_neighbors", bb, 2.8, 7, 10, fake, fake, 8, fake, fake, fake,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_build_neighbors", bb, 2.8, 0, 10, fake, fake, 0, fake, fake, fake,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_build_neighbors", bb, 5.1, 0, 10, fake, fake, 8, fake, fake, fake,
+                None) == lib.EBOX
+    # forces: bad precision, ntypes out of range, missing types for ntypes > 1, rc <= 0
+    args = lambda prec, kind, rc, nt, typ: (bb, prec, kind, rc, nt, fake, fake, 10, fake, typ,
+                                           fake, fake, 8, fake, None, None, None, 0, None)
+    assert call(lib, "ljmd_compute_forces", *args(5, 0, 2.5, 1, None)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces", *args(0, 0, 2.5, 9, fake)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces", *args(0, 0, 2.5, 2, None)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces", *args(0, 0, 0.0, 1, None)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces", *args(0, 3, 2.5, 1, None)) == lib.EINVAL
+    # energy requested without workspace
+    assert call(lib, "ljmd_compute_forces", bb, 0, 0, 2.5, 1, fake, fake, 10, fake, None, fake,
+                fake, 8, fake, fake, fake, None, 0, None) == lib.EWORKSPACE
+    # integrate: bad stage, zero dt, bad mass
+    assert call(lib, "ljmd_integrate", 3, 0.005, 1.0, bb, 10, fake, fake, fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_integrate", 0, 0.0, 1.0, bb, 10, fake, fake, fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_integrate", 0, 0.005, -1.0, bb, 10, fake, fake, fake, None, None, 0,
+                None) == lib.EINVAL
+    # backward: accumulate flag, missing gradient outputs
+    assert call(lib, "ljmd_force_backward", bb, 0, 2.5, 1, fake, fake, 10, fake, None, fake, fake,
+                8, fake, fake, fake, fake, 2, fake, 1 << 20, None) == lib.EINVAL
+    assert call(lib, "ljmd_force_backward", bb, 0, 2.5, 1, fake, fake, 10, fake, None, fake, fake,
+                8, fake, fake, None, fake, 0, fake, 1 << 20, None) == lib.EINVAL
+    assert call(lib, "ljmd_scatter_rows", 10, 0, fake, fake, fake, None) == lib.EINVAL
+    assert call(lib, "ljmd_gather_rows", -1, 3, fake, fake, fake, None) == lib.EINVAL
+    assert call(lib, "ljmd_traj_loss", bb, 10, fake, fake, fake, None, fake, 1 << 20,
+                None) == lib.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2109_09056_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libljmd.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load()
+
+
+def test_ops_reject_cpu_tensors():
+    import torch
+    from paper_2109_09056_amd import ops
+    x = torch.zeros(4, 3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        ops.bin((10.0, 10.0, 10.0), 2.8, x)
+    _ = np  # numpy used by other tests in this module family

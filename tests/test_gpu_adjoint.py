@@ -1,0 +1,187 @@
+"""Adjoint parity: force VJP vs the oracle, autograd, finite differences, and
+checkpointed backprop through a short trajectory.  The oracle only ever sees
+generator inputs in the caller's atom order; GPU results are mapped back to
+that order through the ids the sort returns."""
+import numpy as np
+import pytest
+
+import lj_inputs as li
+from helpers import gpu_device, max_rel_vec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def T(a, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+@pytest.fixture(scope="module")
+def fm(dev, orc):
+    """32,000 atoms, two types: force-matching loss against perturbed-parameter targets."""
+    from paper_2109_09056_amd import autograd, ops
+    w = li.WORKLOADS["lj32k_fm"]
+    x, ty = li.positions(w), li.types(w)
+    eps, sig = li.params(w)
+    et, st = li.perturbed_params(w)
+    lst = orc.neighbor_lists(x, w.box, w.rlist)
+    Ft, _, _ = orc.forces_list(x, w.box, w.rc, *lst, et, st, ty)
+    fc = autograd.ForceContext(w.box, x, ty, rc=w.rc, skin=w.skin, precision=ops.FP64, device=dev)
+    return dict(w=w, fc=fc, x=x, ty=ty, eps=eps, sig=sig, Ft=Ft, lst=lst)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_force_vjp_vs_oracle(dev, orc, fm, prec):
+    from paper_2109_09056_amd import ops
+    w, fc = fm["w"], fm["fc"]
+    g = np.random.default_rng(7).normal(size=fm["x"].shape)
+    gxo, geo, gso = orc.force_vjp(fm["x"], w.box, w.rc, g, fm["eps"], fm["sig"], fm["ty"],
+                                  *fm["lst"])
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    gx, ge, gs = ops.force_backward(w.box, P, w.rc, T(fm["eps"], dev), T(fm["sig"], dev), fc.x,
+                                    fc.types, fc.nl.nbr, fc.nl.nnbr, fc.nl.maxn,
+                                    fc.sorted_rows(g))
+    gx = fc.caller_rows(gx).cpu().numpy()
+    ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    ex = max_rel_vec(gx, gxo)
+    ee = np.abs(ge - geo).max() / np.abs(geo).max()
+    es = np.abs(gs - gso).max() / np.abs(gso).max()
+    print(f"[{prec}] vjp rel err x {ex:.2e} eps {ee:.2e} sigma {es:.2e}")
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    assert ex <= tol and ee <= tol and es <= tol
+
+
+def test_force_vjp_accumulate_and_deterministic(dev, fm):
+    import torch
+    from paper_2109_09056_amd import ops
+    w, fc = fm["w"], fm["fc"]
+    g = fc.sorted_rows(np.random.default_rng(3).normal(size=fm["x"].shape))
+    args = (w.box, ops.FP64, w.rc, T(fm["eps"], dev), T(fm["sig"], dev), fc.x, fc.types,
+            fc.nl.nbr, fc.nl.nnbr, fc.nl.maxn, g)
+    a = [t.clone() for t in ops.force_backward(*args)]
+    b = ops.force_backward(*args)
+    for p, q in zip(a, b):
+        assert torch.equal(p, q)
+    c = ops.force_backward(*args, gx=b[0].clone(), geps=b[1].clone(), gsigma=b[2].clone(),
+                           accumulate=True)
+    for p, q in zip(a, c):
+        assert torch.allclose(2 * p, q, rtol=1e-14, atol=0)
+
+
+def test_autograd_force_matching_loss(dev, orc, fm):
+    """loss = sum |F - F_target|^2 through LJForce; gradients vs the oracle and FD."""
+    import torch
+    from paper_2109_09056_amd import autograd
+    w, fc = fm["w"], fm["fc"]
+    x = fc.x.clone().requires_grad_(True)
+    eps = T(fm["eps"], dev).requires_grad_(True)
+    sig = T(fm["sig"], dev).requires_grad_(True)
+    Ft = fc.sorted_rows(fm["Ft"])
+    F = autograd.lj_forces(x, eps, sig, fc)
+    loss = ((F - Ft) ** 2).sum()
+    loss.backward()
+    Fo, _, _ = orc.forces_list(fm["x"], w.box, w.rc, *fm["lst"], fm["eps"], fm["sig"], fm["ty"])
+    gxo, geo, gso = orc.force_vjp(fm["x"], w.box, w.rc, 2.0 * (Fo - fm["Ft"]), fm["eps"],
+                                  fm["sig"], fm["ty"], *fm["lst"])
+    assert float(loss.item()) == pytest.approx(((Fo - fm["Ft"]) ** 2).sum(), rel=1e-11)
+    assert max_rel_vec(fc.caller_rows(x.grad).cpu().numpy(), gxo) <= 1e-11
+    np.testing.assert_allclose(eps.grad.cpu().numpy(), geo, rtol=1e-11)
+    np.testing.assert_allclose(sig.grad.cpu().numpy(), gso, rtol=1e-11)
+
+    def L_of(xx, ee, ss):  # central finite differences of the GPU loss itself (FP64 path)
+        with torch.no_grad():
+            return float(((autograd.lj_forces(xx, ee, ss, fc) - Ft) ** 2).sum().item())
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        i, k = int(rng.integers(0, x.shape[0])), int(rng.integers(0, 3))
+        xp, xm = x.detach().clone(), x.detach().clone()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = (L_of(xp, eps.detach(), sig.detach()) - L_of(xm, eps.detach(), sig.detach())) / (2 * h)
+        assert x.grad[i, k].item() == pytest.approx(fd, rel=1e-5, abs=1e-4)
+    hp = 1e-7
+    for p in range(3):
+        for which in (0, 1):
+            up = [eps.detach().clone(), sig.detach().clone()]
+            dn = [eps.detach().clone(), sig.detach().clone()]
+            up[which][p] += hp
+            dn[which][p] -= hp
+            fd = (L_of(x.detach(), *up) - L_of(x.detach(), *dn)) / (2 * hp)
+            grad = (eps.grad if which == 0 else sig.grad)[p].item()
+            assert grad == pytest.approx(fd, rel=1e-5)
+
+
+def test_trajectory_backprop_vs_oracle_small(dev, orc):
+    """256 atoms, two types, 20 steps, checkpoints every 5, FP64: GPU gradient vs the
+    oracle's (uncheckpointed, unmerged) discrete adjoint."""
+    from paper_2109_09056_amd import ops, trajectory
+    w = li.Workload("traj_small", 4, cells=4, ntypes=2, steps=20, checkpoint_every=5)
+    x0, v0, ty = li.positions(w), li.velocities(w), li.types(w)
+    eps, sig = li.params(w)
+    et, st = li.perturbed_params(w)
+    _, _, xref, _ = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, et, st, ty)
+    r = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref, steps=20,
+                                       checkpoint_every=5, precision=ops.FP64, device=dev)
+    assert r.recompute_bitwise
+    xs, vT, xT_unw, lst = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, eps, sig, ty)
+    d = xT_unw - xref
+    gx0, gv0, ge, gs = orc.trajectory_adjoint(xs, w.box, w.rc, w.dt, eps, sig, d,
+                                              np.zeros_like(d), ty, lst)
+    assert float(r.loss.item()) == pytest.approx(0.5 * (d * d).sum(), rel=1e-9)
+    assert max_rel_vec(r.gx0.cpu().numpy(), gx0) <= 1e-9
+    assert max_rel_vec(r.gv0.cpu().numpy(), gv0) <= 1e-9
+    np.testing.assert_allclose(r.geps.cpu().numpy(), ge, rtol=1e-9)
+    np.testing.assert_allclose(r.gsigma.cpu().numpy(), gs, rtol=1e-9)
+
+
+def test_trajectory_backprop_256k_fd(dev):
+    """256,000 atoms, two types, 20 steps, checkpoints every 5: FD on the FP64 path
+    (a property at any size), and the mixed-path gradient error vs the FP64 gradient."""
+    from paper_2109_09056_amd import ops, trajectory
+    w = li.WORKLOADS["lj256k_traj"]
+    x0, v0, ty = li.positions(w), li.velocities(w), li.types(w)
+    eps, sig = li.params(w)
+    et, st = li.perturbed_params(w)
+    xref = trajectory.run_trajectory(w.box, x0, v0, ty, et, st, steps=w.steps,
+                                     device=dev).cpu().numpy()
+    r64 = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref, steps=w.steps,
+                                         checkpoint_every=w.checkpoint_every,
+                                         precision=ops.FP64, device=dev)
+    assert r64.recompute_bitwise
+
+    def loss_at(x, e, s):
+        xt = trajectory.run_trajectory(w.box, x, v0, ty, e, s, steps=w.steps, device=dev)
+        d = xt.cpu().numpy() - xref
+        d -= w.box * np.round(d / w.box)
+        return 0.5 * (d * d).sum()
+
+    gx = r64.gx0.cpu().numpy()
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    for _ in range(3):
+        i, k = int(rng.integers(0, w.natoms)), int(rng.integers(0, 3))
+        xp, xm = x0.copy(), x0.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = (loss_at(xp, eps, sig) - loss_at(xm, eps, sig)) / (2 * h)
+        assert gx[i, k] == pytest.approx(fd, rel=1e-4, abs=1e-7)
+    hp = 1e-7
+    for p in range(3):
+        ep, em = eps.copy(), eps.copy()
+        ep[p] += hp
+        em[p] -= hp
+        fd = (loss_at(x0, ep, sig) - loss_at(x0, em, sig)) / (2 * hp)
+        assert r64.geps[p].item() == pytest.approx(fd, rel=1e-4)
+    rm = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref, steps=w.steps,
+                                        checkpoint_every=w.checkpoint_every,
+                                        precision=ops.MIXED, device=dev)
+    assert rm.recompute_bitwise
+    rel = np.linalg.norm(rm.gx0.cpu().numpy() - gx) / np.linalg.norm(gx)
+    print(f"mixed vs FP64 trajectory gradient: rel L2 {rel:.3e}")
+    assert rel < 1e-3

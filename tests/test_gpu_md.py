@@ -1,0 +1,151 @@
+"""Integrator and MD-loop parity of the HIP path against the oracle."""
+import numpy as np
+import pytest
+
+import lj_inputs as li
+from helpers import gpu_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def T(a, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def test_integrate_stages_bitwise(dev, orc):
+    import torch
+    from paper_2109_09056_amd import ops
+    rng = np.random.default_rng(0)
+    L = np.array([10.0, 11.0, 12.0])
+    n = 1000
+    x = rng.uniform(0, 1, (n, 3)) * L
+    x[:3] = [[np.nextafter(10.0, 0), 0.0, 5.0], [0.0, 1e-18, 5.0], [5.0, 5.0, 11.9999999]]
+    v = rng.normal(size=(n, 3)) * 50.0
+    F = rng.normal(size=(n, 3)) * 30.0
+    for mass in (1.0, 2.5):
+        xg, vg = T(x, dev), T(v, dev)
+        ke = torch.zeros(1, dtype=torch.float64, device=dev)
+        ops.integrate(ops.KICK_DRIFT, 0.005, mass, L, xg, vg, T(F, dev))
+        xo, vo = x.copy(), v.copy()
+        orc.kick_drift(xo, vo, F, 0.005, L, mass=mass)
+        assert np.array_equal(xg.cpu().numpy(), xo)
+        assert np.array_equal(vg.cpu().numpy(), vo)
+        assert np.all(xo >= 0) and np.all(xo < L)
+        ops.integrate(ops.KICK, 0.005, mass, L, xg, vg, T(F, dev), ke=ke)
+        orc.kick(vo, F, 0.005, mass=mass)
+        assert np.array_equal(vg.cpu().numpy(), vo)
+        assert float(ke.item()) == pytest.approx(0.5 * mass * (vo * vo).sum(), rel=1e-13)
+
+
+def test_nve_lj256_matches_oracle_trajectory(dev, orc):
+    """100 FP64 steps with rebuilds every 20: GPU and oracle Verlet-mirror trajectories agree."""
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj256"]
+    s = li.make_system(w)
+    sim = md.LJSim(w.box, precision=ops.FP64, kind=ops.FULL, dt=w.dt, device=dev)
+    sim.load(s["x"], s["v"])
+    th0 = sim.thermo()
+    rec = {20, 50, 100}
+    got = {}
+    for k in range(1, 101):
+        sim.step(1)
+        if k in rec:
+            got[k] = (sim.in_caller_order(sim.x).cpu().numpy(), sim.thermo())
+    _, _, _, thermo, snaps, _ = orc.run_nve(s["x"], s["v"], w.box, w.rc, w.rlist, w.dt, 100,
+                                            mode="verlet", record=rec)
+    for k in sorted(rec):
+        xg, th = got[k]
+        d = xg - snaps[k][0]
+        d -= w.box * np.round(d / w.box)
+        assert np.abs(d).max() < 1e-9, (k, np.abs(d).max())
+        pe_o, ke_o = thermo[k][1], thermo[k][2]
+        assert th["pe"] == pytest.approx(pe_o, rel=1e-10)
+        assert th["ke"] == pytest.approx(ke_o, rel=1e-10)
+    assert th0["temp"] == pytest.approx(1.44, rel=1e-12)
+
+
+def pairs_within(x, L, rc):
+    """Number of unordered pairs closer than rc (NumPy brute force)."""
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    r2 = (d * d).sum(-1)
+    return int((np.triu(r2 < rc * rc, 1)).sum())
+
+
+def test_nve_energy_and_momentum_lj256(dev, orc):
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj256"]
+    s = li.make_system(w)
+    u_rc = orc.pair_energy(w.rc * (1 - 1e-15))[0]
+    for prec in (ops.FP64, ops.MIXED):
+        sim = md.LJSim(w.box, precision=prec, kind=ops.FULL, dt=w.dt, device=dev)
+        sim.load(s["x"], s["v"])
+        esh = []
+        for _ in range(10):
+            sim.step(10)
+            th = sim.thermo()
+            esh.append(th["etot"] - pairs_within(sim.x.cpu().numpy(), w.box, w.rc) * u_rc)
+        esh = np.array(esh)
+        assert np.abs(esh - esh[0]).max() / w.natoms < 1e-3
+        assert sim.v.sum(dim=0).abs().max().item() < 1e-10
+
+
+def test_md_bitwise_repeatable(dev):
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    outs = []
+    for _ in range(2):
+        sim = md.LJSim(w.box, precision=ops.MIXED, kind=ops.FULL, dt=w.dt, device=dev)
+        sim.load(s["x"], s["v"])
+        sim.step(45)
+        outs.append((sim.x.clone(), sim.v.clone(), sim.ev.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def oracle_32k_run(orc):
+    """The oracle's own Verlet-list trajectory of the 32,000-atom liquid, 100 steps."""
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    _, _, _, thermo, snaps, _ = orc.run_nve(s["x"], s["v"], w.box, w.rc, w.rlist, w.dt, 100,
+                                            mode="verlet", record={20, 100})
+    return w, s, thermo, snaps
+
+
+@pytest.mark.parametrize("prec,kind", [("fp64", "full"), ("mixed", "full"), ("fp64", "half"),
+                                       ("mixed", "half")])
+def test_lj32k_trajectory_vs_oracle(dev, oracle_32k_run, prec, kind):
+    """32,000 atoms, rebuild every 20 steps: positions and energies track the oracle's own
+    trajectory at steps 20 and 100, then 900 more steps keep momentum and energy."""
+    from paper_2109_09056_amd import md, ops
+    w, s, thermo, snaps = oracle_32k_run
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    K = ops.FULL if kind == "full" else ops.HALF
+    sim = md.LJSim(w.box, precision=P, kind=K, dt=w.dt, device=dev)
+    sim.load(s["x"], s["v"])
+    tol = {20: 1e-11, 100: 1e-9} if P == ops.FP64 else {20: 1e-6, 100: 1e-4}
+    done = 0
+    for snap in (20, 100):
+        sim.step(snap - done)
+        done = snap
+        d = sim.in_caller_order(sim.x).cpu().numpy() - snaps[snap][0]
+        d -= w.box * np.round(d / w.box)
+        assert np.abs(d).max() < tol[snap], (snap, np.abs(d).max())
+        th = sim.thermo()
+        etol = 1e-10 if P == ops.FP64 else 1e-6
+        assert th["pe"] == pytest.approx(thermo[snap][1], rel=etol)
+    e100 = sim.thermo()["etot"]
+    sim.step(900)
+    th = sim.thermo()
+    assert th["builds"] == 51 and np.isfinite(th["etot"])
+    assert abs(th["etot"] - e100) / w.natoms < 5e-3
+    assert sim.v.sum(dim=0).abs().max().item() < 1e-9

@@ -1,0 +1,374 @@
+"""Parity of the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Bars: bin permutation and cell starts bit-exact; neighbor sets identical as
+sorted sets of original-id pairs; FP64 forces max_i |dF_i| <= 1e-12 max_i |F_i|
+and per-atom energy, E and each virial component to relative 1e-12; mixed
+forces max_i |dF_i| <= 1e-5 F_rms and per-atom energy relative 1e-6.
+"""
+import numpy as np
+import pytest
+
+import lj_inputs as li
+from helpers import gpu_device, gpu_pairs_by_id, max_rel_vec, oracle_pairs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_F_TOL = 1e-5
+MIXED_E_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def T(a, dev, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev, dtype=dtype)
+
+
+def gas(n, L, seed):
+    return li.random_gas(n, L, seed)
+
+
+def clumped(n_bulk, n_clump, L, seed):
+    """Bulk gas plus a dense clump that overfills a few cells (ragged, big candidate sets)."""
+    rng = np.random.default_rng(seed)
+    x = li.random_gas(n_bulk, L, seed)
+    c = rng.uniform(0.3, 0.7, size=3) * np.asarray(L)
+    clump = c + rng.uniform(-1.2, 1.2, size=(n_clump, 3))
+    return np.concatenate([x, clump])
+
+
+def gpu_sort(dev, x, L, rlist, v=None, types=None):
+    import torch
+    from paper_2109_09056_amd import ops
+    xs, vs, ts, ids, cs = ops.bin(L, rlist, T(x, dev, torch.float64),
+                                  None if v is None else T(v, dev, torch.float64),
+                                  None if types is None else T(types, dev, torch.int32))
+    return xs, vs, ts, ids, cs
+
+
+# ---------------------------------------------------------------------- bin --
+
+BIN_CASES = [
+    ("lj256", None), ("lj32k", None), ("gas_ragged", (331, (6.0, 7.5, 9.0))),
+    ("gas_one", (1, (6.0, 6.0, 6.0))), ("gas_five", (5, (9.0, 9.1, 9.2))),
+    ("clump", None),
+]
+
+
+@pytest.mark.parametrize("name,spec", BIN_CASES)
+def test_bin_matches_oracle(dev, orc, name, spec):
+    if name in li.WORKLOADS:
+        w = li.WORKLOADS[name]
+        x, L = li.positions(w), w.box
+    elif name == "clump":
+        L = np.array([14.0, 15.0, 16.0])
+        x = clumped(900, 700, L, 5)
+    else:
+        n, L = spec
+        x = gas(n, L, 11)
+    L = np.asarray(L, dtype=np.float64)
+    perm, cell_start, nc = orc.bin_order(x, np.arange(x.shape[0]), L, 2.8)
+    xs, _, _, ids, cs = gpu_sort(dev, x, L, 2.8)
+    assert np.array_equal(ids.cpu().numpy(), perm)
+    assert np.array_equal(cs.cpu().numpy().astype(np.int64), cell_start)
+    assert np.array_equal(xs.cpu().numpy(), x[perm])
+
+
+def test_bin_permutes_every_field_and_keeps_given_ids(dev, orc):
+    import torch
+    from paper_2109_09056_amd import ops
+    L = np.array([9.0, 10.0, 11.5])
+    x = gas(700, L, 3)
+    rng = np.random.default_rng(1)
+    ids = rng.permutation(700).astype(np.int64) * 3 + 11
+    v = rng.normal(size=(700, 3))
+    ty = rng.integers(0, 3, 700).astype(np.int32)
+    perm, cell_start, _ = orc.bin_order(x, ids, L, 2.8)
+    xs, vs, ts, io, cs = ops.bin(L, 2.8, T(x, dev), T(v, dev), T(ty, dev), T(ids, dev))
+    assert np.array_equal(io.cpu().numpy(), ids[perm])
+    assert np.array_equal(vs.cpu().numpy(), v[perm])
+    assert np.array_equal(ts.cpu().numpy(), ty[perm])
+    assert np.array_equal(cs.cpu().numpy(), cell_start)
+    # deterministic: a second sort of the sorted output is the identity
+    xs2, _, _, io2, _ = ops.bin(L, 2.8, xs, None, None, io)
+    assert torch.equal(xs2, xs) and torch.equal(io2, io)
+
+
+def test_bin_empty(dev):
+    import torch
+    from paper_2109_09056_amd import ops
+    x = torch.zeros(0, 3, dtype=torch.float64, device=dev)
+    xs, _, _, ids, cs = ops.bin((9.0, 9.0, 9.0), 2.8, x)
+    assert xs.shape == (0, 3) and int(cs.cpu().max()) == 0
+
+
+# ---------------------------------------------------------------- neighbors --
+
+def gpu_lists(dev, x, L, rlist, kind, maxn=None):
+    from paper_2109_09056_amd import md
+    xs, _, _, ids, cs = gpu_sort(dev, x, L, rlist)
+    nl = md.NeighborList(L, rlist, kind, maxn=maxn, device=dev).build(xs, cs)
+    return nl, ids, xs
+
+
+NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny"]
+
+
+def case_positions(name):
+    if name in li.WORKLOADS:
+        w = li.WORKLOADS[name]
+        return li.positions(w), w.box
+    if name == "gas_ragged":
+        L = np.array([6.0, 7.5, 9.0])
+        return gas(331, L, 17), L
+    if name == "gas_long":
+        L = np.array([5.8, 5.8, 17.0])
+        return gas(450, L, 19), L
+    if name == "clump":
+        L = np.array([14.0, 15.0, 16.0])
+        return clumped(900, 700, L, 5), L
+    if name == "tiny":
+        L = np.array([6.0, 6.0, 6.0])
+        return gas(3, L, 23), L
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("kind", ["full", "half"])
+@pytest.mark.parametrize("name", NBR_CASES)
+def test_neighbor_sets_match_oracle(dev, orc, name, kind):
+    from paper_2109_09056_amd import ops
+    x, L = case_positions(name)
+    k = ops.FULL if kind == "full" else ops.HALF
+    nl, ids, _ = gpu_lists(dev, x, L, 2.8, k)
+    got = gpu_pairs_by_id(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn,
+                          ids.cpu().numpy(), half=(kind == "half"))
+    off, nb = orc.neighbor_lists(x, L, 2.8)
+    want = oracle_pairs(off, nb, half=(kind == "half"))
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    if kind == "half":
+        # each unordered pair stored once, owned by the lower sorted index
+        rows_total = int(nl.nnbr.sum().item())
+        assert rows_total == want.shape[0]
+
+
+def test_neighbor_capacity_overflow_reported(dev, orc):
+    from paper_2109_09056_amd import ops
+    w = li.WORKLOADS["lj256"]
+    x = li.positions(w)
+    xs, _, _, ids, cs = gpu_sort(dev, x, w.box, w.rlist)
+    nbr, nnbr, mc = ops.build_neighbors(w.box, w.rlist, ops.FULL, xs, cs, 10)
+    off, nb = orc.neighbor_lists(x, w.box, w.rlist)
+    assert int(mc.item()) == int(np.diff(off).max())
+    assert int(nnbr.max().item()) == 10
+    # the driver grows maxn until nothing is cut
+    from paper_2109_09056_amd import md
+    nl = md.NeighborList(w.box, w.rlist, ops.FULL, maxn=10, device=dev).build(xs, cs)
+    assert nl.overflows == 1 and nl.maxn >= int(np.diff(off).max())
+    got = gpu_pairs_by_id(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn, ids.cpu().numpy())
+    assert np.array_equal(got, oracle_pairs(off, nb))
+
+
+# ------------------------------------------------------------------- forces --
+
+def gpu_forces(dev, x, L, precision, kind, eps=(1.0,), sigma=(1.0,), types=None, rc=2.5,
+               skin=0.3):
+    import torch
+    from paper_2109_09056_amd import ops
+    nl, ids, xs = gpu_lists(dev, x, L, rc + skin, kind)
+    n = x.shape[0]
+    ty = T(types if types is not None else np.zeros(n, np.int32), dev, torch.int32)
+    ts = ops.gather_rows(ids, ty.to(torch.float64)).to(torch.int32)
+    F, e, ev = ops.compute_forces(L, precision, kind, rc, T(eps, dev, torch.float64),
+                                  T(sigma, dev, torch.float64), xs, ts, nl.nbr, nl.nnbr, nl.maxn)
+    F = ops.scatter_rows(ids, F).cpu().numpy()
+    e = ops.scatter_rows(ids, e).cpu().numpy()
+    return F, e, ev.cpu().numpy()
+
+
+def check_fp64(F, e, ev, Fo, eo, Wo):
+    assert max_rel_vec(F, Fo) <= FP64_TOL
+    assert np.abs(e - eo).max() <= FP64_TOL * np.abs(eo).max()
+    assert abs(ev[0] - eo.sum()) <= FP64_TOL * abs(eo.sum())
+    wscale = np.abs(Wo[:3]).max()
+    assert np.abs(ev[1:] - Wo).max() <= FP64_TOL * wscale
+
+
+def check_mixed(F, e, Fo, eo):
+    frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+    err_f = np.linalg.norm(F - Fo, axis=1).max() / frms
+    err_e = (np.abs(e - eo) / np.maximum(np.abs(eo), 1e-3)).max()
+    assert err_f <= MIXED_F_TOL, err_f
+    assert err_e <= MIXED_E_TOL, err_e
+    return err_f, err_e
+
+
+SYSTEMS = {
+    "lj256": lambda: (li.positions(li.WORKLOADS["lj256"]), li.WORKLOADS["lj256"].box, None, [1.0],
+                      [1.0]),
+    "lj32k": lambda: (li.positions(li.WORKLOADS["lj32k"]), li.WORKLOADS["lj32k"].box, None, [1.0],
+                      [1.0]),
+    "lj32k_fm": lambda: (li.positions(li.WORKLOADS["lj32k_fm"]), li.WORKLOADS["lj32k_fm"].box,
+                         li.types(li.WORKLOADS["lj32k_fm"]), *li.params(li.WORKLOADS["lj32k_fm"])),
+    "three_types": lambda: (li.positions(li.WORKLOADS["lj256"]), li.WORKLOADS["lj256"].box,
+                            (np.arange(256) % 3).astype(np.int32),
+                            np.array([1.0, 0.9, 1.1, 1.2, 0.8, 1.05]),
+                            np.array([1.0, 0.95, 1.02, 1.05, 0.92, 0.97])),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_forces_cache(orc):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            x, L, ty, eps, sig = SYSTEMS[name]()
+            cache[name] = (x, L, ty, eps, sig, orc.forces(x, L, 2.5, eps, sig, ty))
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("kind", ["full", "half"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_forces_fp64(dev, oracle_forces_cache, name, kind):
+    from paper_2109_09056_amd import ops
+    x, L, ty, eps, sig, (Fo, eo, Wo, _) = oracle_forces_cache(name)
+    k = ops.FULL if kind == "full" else ops.HALF
+    F, e, ev = gpu_forces(dev, x, L, ops.FP64, k, eps, sig, ty)
+    check_fp64(F, e, ev, Fo, eo, Wo)
+
+
+@pytest.mark.parametrize("kind", ["full", "half"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_forces_mixed(dev, oracle_forces_cache, name, kind):
+    from paper_2109_09056_amd import ops
+    x, L, ty, eps, sig, (Fo, eo, Wo, _) = oracle_forces_cache(name)
+    k = ops.FULL if kind == "full" else ops.HALF
+    F, e, ev = gpu_forces(dev, x, L, ops.MIXED, k, eps, sig, ty)
+    err_f, err_e = check_mixed(F, e, Fo, eo)
+    print(f"[{name}/{kind}] mixed max|dF|/Frms = {err_f:.3e}  max rel de = {err_e:.3e}")
+    assert abs(ev[0] - eo.sum()) <= 1e-6 * abs(eo.sum())
+
+
+def test_forces_full_list_bitwise_deterministic(dev):
+    import torch
+    from paper_2109_09056_amd import ops
+    w = li.WORKLOADS["lj32k"]
+    x = li.positions(w)
+    nl, ids, xs = gpu_lists(dev, x, w.box, w.rlist, ops.FULL)
+    one = T([1.0], dev, torch.float64)
+    ty = torch.zeros(x.shape[0], dtype=torch.int32, device=dev)
+    for prec in (ops.FP64, ops.MIXED):
+        a = ops.compute_forces(w.box, prec, ops.FULL, 2.5, one, one, xs, ty, nl.nbr, nl.nnbr,
+                               nl.maxn)
+        a = [t.clone() for t in a]
+        b = ops.compute_forces(w.box, prec, ops.FULL, 2.5, one, one, xs, ty, nl.nbr, nl.nnbr,
+                               nl.maxn)
+        for p, q in zip(a, b):
+            assert torch.equal(p, q)
+
+
+def test_forces_without_energy_outputs(dev, oracle_forces_cache):
+    import torch
+    from paper_2109_09056_amd import ops
+    x, L, ty, eps, sig, (Fo, eo, Wo, _) = oracle_forces_cache("lj256")
+    nl, ids, xs = gpu_lists(dev, x, L, 2.8, ops.FULL)
+    one = T([1.0], dev, torch.float64)
+    tz = torch.zeros(x.shape[0], dtype=torch.int32, device=dev)
+    F, e, ev = ops.compute_forces(L, ops.FP64, ops.FULL, 2.5, one, one, xs, tz, nl.nbr, nl.nnbr,
+                                  nl.maxn, want_energy=False)
+    assert e is None and ev is None
+    assert max_rel_vec(ops.scatter_rows(ids, F).cpu().numpy(), Fo) <= FP64_TOL
+
+
+def test_forces_empty(dev):
+    import torch
+    from paper_2109_09056_amd import ops
+    x = torch.zeros(0, 3, dtype=torch.float64, device=dev)
+    one = T([1.0], dev, torch.float64)
+    nbr = torch.zeros(64 * 8, dtype=torch.int32, device=dev)
+    nnbr = torch.zeros(0, dtype=torch.int32, device=dev)
+    t = torch.zeros(0, dtype=torch.int32, device=dev)
+    for kind in (ops.FULL, ops.HALF):
+        F, e, ev = ops.compute_forces((9.0, 9.0, 9.0), ops.FP64, kind, 2.5, one, one, x, t, nbr,
+                                      nnbr, 8)
+        assert F.shape == (0, 3) and float(ev.abs().sum().item()) == 0.0
+
+
+# ------------------------------------------------------- 500k, sampled rows --
+
+@pytest.fixture(scope="module")
+def big(dev):
+    """500,000-atom jittered fcc liquid start, sorted and listed exactly as the benchmark does."""
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj500k"]
+    s = li.make_system(w)
+    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, kind=ops.FULL, dt=w.dt,
+                   rebuild_every=w.rebuild_every, device=dev)
+    sim.load(s["x"], s["v"])
+    return w, s, sim
+
+
+def test_500k_sampled_neighbors_and_forces(dev, orc, big):
+    """Sampled atoms of the 500k start: oracle rows over all 500k atoms, by original id."""
+    import torch
+    from helpers import decode_rows
+    from paper_2109_09056_amd import ops
+    w, s, sim = big
+    n = w.natoms
+    x = s["x"]
+    ids = sim.ids.cpu().numpy()
+    assert np.array_equal(np.sort(ids), np.arange(n))
+    pos_of = np.empty(n, dtype=np.int64)
+    pos_of[ids] = np.arange(n)
+    atoms = np.sort(np.random.default_rng(0).choice(n, 1500, replace=False))  # original ids
+    rows = decode_rows(sim.nl.nbr.cpu().numpy(), sim.nl.nnbr.cpu().numpy(), sim.nl.maxn)
+    off, nb = orc.neighbor_lists(x, w.box, w.rlist, sel=atoms)
+    for k, a in enumerate(atoms):
+        got = np.sort(ids[rows[pos_of[a]]])
+        assert np.array_equal(got, nb[off[k]:off[k + 1]])
+    Fo, eo, _, _ = orc.forces(x, w.box, w.rc, sel=atoms)
+    one = T([1.0], dev, torch.float64)
+    for prec in (ops.MIXED, ops.FP64):
+        F, e, _ = ops.compute_forces(w.box, prec, ops.FULL, w.rc, one, one, sim.x, sim.types,
+                                     sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+        Fs = F.cpu().numpy()[pos_of[atoms]]
+        es = e.cpu().numpy()[pos_of[atoms]]
+        if prec == ops.FP64:
+            assert (np.linalg.norm(Fs - Fo, axis=1).max()
+                    <= FP64_TOL * np.linalg.norm(Fo, axis=1).max())
+            assert np.abs(es - eo).max() <= FP64_TOL * np.abs(eo).max()
+        else:
+            frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+            assert np.linalg.norm(Fs - Fo, axis=1).max() <= MIXED_F_TOL * frms
+            assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
+
+
+def test_500k_steps_properties(dev, big):
+    """40 steps (two rebuilds) at 500k: momentum stays zero, mixed and FP64 runs from the
+    same start stay together, and the full list stays symmetric."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w, s, sim = big
+    ref = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.FP64, kind=ops.FULL, dt=w.dt,
+                   device=dev)
+    ref.load(s["x"], s["v"])
+    e0 = sim.thermo()["etot"]
+    sim.step(40)
+    ref.step(40)
+    th = sim.thermo()
+    assert th["builds"] >= 3 and np.isfinite(th["etot"])
+    assert abs(th["etot"] - e0) / w.natoms < 1e-2
+    assert sim.v.sum(dim=0).abs().max().item() < 1e-8
+    xm = sim.in_caller_order(sim.x).cpu().numpy()
+    xf = ref.in_caller_order(ref.x).cpu().numpy()
+    d = xm - xf
+    d -= w.box * np.round(d / w.box)
+    assert np.abs(d).max() < 1e-5
+    nn = sim.nl.nnbr.to(torch.int64)
+    assert int(nn.sum().item()) % 2 == 0
