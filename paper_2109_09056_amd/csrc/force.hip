@@ -9,8 +9,9 @@
 //   u   = sr6 (4 eps sr6 - 4 eps)
 // FP64 form: all of it in FP64 (reciprocal = hardware estimate + two Newton
 // steps).  Mixed form: displacement, r^2 and the cutoff test in FP64 (so the
-// pair set is the FP64 one), then ri2, sr6, s, u and the pair force s*d in
-// FP32, promoted to FP64 for the accumulation of F, e, E and W.
+// pair set is the FP64 one), then ri2, sr6 and the pair scalars s and u in
+// FP32; s and u are promoted once, and the pair force s*d (with the FP64 d)
+// and the accumulation of F, e, E and W are FP64.
 //
 // FULL list: lane i of the grid owns atom i and walks its row of the tile
 // (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l], one coalesced
@@ -87,10 +88,10 @@ __device__ __forceinline__ PairOut lj_pair(double dx, double dy, double dz, doub
     const float ri2 = recip32((float)r2);
     const float sr2 = (float)c.sig2 * ri2;
     const float sr6 = sr2 * sr2 * sr2;
-    const float s = ri2 * sr6 * __builtin_fmaf((float)c.c12, sr6, -(float)c.c6);
-    o.fx = (double)(s * (float)dx);
-    o.fy = (double)(s * (float)dy);
-    o.fz = (double)(s * (float)dz);
+    const double s = (double)(ri2 * sr6 * __builtin_fmaf((float)c.c12, sr6, -(float)c.c6));
+    o.fx = s * dx;
+    o.fy = s * dy;
+    o.fz = s * dz;
     if constexpr (EV) o.u = (double)(sr6 * __builtin_fmaf((float)c.e4, sr6, -(float)c.e4));
   } else {
     const double ri2 = recip64(r2);
