@@ -44,7 +44,22 @@ def parse():
                     help="time the headline path only (no FP64 run, no bwd/fwd ratios)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target length of the oracle's CPU sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 512 MiB (x5), to calibrate HBM "
+                         "byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 5}), flush=True)
 
 
 def md_run(w, s, precision, steps, warmup, dev):
@@ -179,6 +194,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(spatial decomposition is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
     import lj_inputs as li

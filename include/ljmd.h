@@ -62,6 +62,7 @@ extern "C" {
 #define LJMD_HALF 1   /* each unordered pair once, owned by the lower sorted index */
 #define LJMD_KICK_DRIFT 0 /* v += dt/2 F/m; x += dt v; wrap x into [0, L) */
 #define LJMD_KICK 1       /* v += dt/2 F/m */
+#define LJMD_KINETIC 2    /* no update: only the kinetic energy 1/2 m sum v^2 into ke */
 
 /* workspace queries (ljmd_workspace_bytes) */
 #define LJMD_OP_BIN 0
@@ -180,6 +181,8 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
  *   stage LJMD_KICK_DRIFT: v += dt/2 F/m; x += dt v; wrap each component:
  *         if x >= L: x -= L, else if x < 0: x += L; then if x >= L: x -= L
  *   stage LJMD_KICK:       v += dt/2 F/m
+ *   stage LJMD_KINETIC:    nothing is updated (x, F may be NULL, dt is ignored);
+ *                          ke is required
  *   ke    device FP64 scalar receiving 1/2 m sum v^2 after the update, or NULL
  *   ws    >= ljmd_workspace_bytes(LJMD_OP_INTEGRATE, n, 0, 0) when ke != NULL
  */

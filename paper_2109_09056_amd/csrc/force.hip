@@ -20,6 +20,8 @@
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
 // column-sum launch (deterministic).
+#include <stdlib.h>
+
 #include "common.h"
 
 namespace ljmd {
@@ -30,6 +32,7 @@ constexpr int kEvStride = 8;  // partial row: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, p
 
 struct ForceArgs {
   BoxK b;
+  double rc;
   double rc2;
   int32_t ntypes;
   const double *eps;
@@ -106,63 +109,116 @@ __device__ __forceinline__ PairOut lj_pair(double dx, double dy, double dz, doub
   return o;
 }
 
-template <bool MIXED, bool T1, bool EV>
+// Accumulators of one atom's row.
+struct Acc {
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+};
+
+// Walk atom i's row, U slots per iteration: the U index loads, then the U
+// position gathers, then the U pair evaluations, so several loads are in
+// flight per lane.  WRAP = false skips the minimum image; the caller only
+// takes that path when every atom of the wavefront is at least rc from all
+// box faces, where any pair closer than rc has the same raw and
+// minimum-image displacement, and any other pair has some |raw component|
+// above L/2 > rc and is rejected by the cutoff test either way.
+template <bool MIXED, bool T1, bool EV, int U, bool WRAP>
+__device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row, int32_t cnt,
+                                         double xi, double yi, double zi, int ti,
+                                         const Coef &c1, const double *tab, Acc &s) {
+  const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
+  const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
+  for (int32_t k = 0; k < cnt; k += U) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t kk = (u == 0 || k + u < cnt) ? k + u : k;
+      j[u] = row[(int64_t)kk * kWave];
+    }
+    double xj[U], yj[U], zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xj[u] = a.x[3 * (int64_t)j[u]];
+      yj[u] = a.x[3 * (int64_t)j[u] + 1];
+      zj[u] = a.x[3 * (int64_t)j[u] + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
+      if constexpr (WRAP) {
+        dx = min_image(dx, L0, iL0);
+        dy = min_image(dy, L1, iL1);
+        dz = min_image(dz, L2, iL2);
+      }
+      const double r2 = dist2(dx, dy, dz);
+      if ((u == 0 || k + u < cnt) && r2 < a.rc2) {
+        Coef c;
+        if constexpr (T1) {
+          c = c1;
+        } else {
+          const double *t = tab + 4 * (ti * a.ntypes + a.type[j[u]]);
+          c = Coef{t[0], t[1], t[2], t[3]};
+        }
+        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
+        s.fx += p.fx;
+        s.fy += p.fy;
+        s.fz += p.fz;
+        if constexpr (EV) {
+          s.e += p.u;
+          s.wxx = __builtin_fma(dx, p.fx, s.wxx);
+          s.wyy = __builtin_fma(dy, p.fy, s.wyy);
+          s.wzz = __builtin_fma(dz, p.fz, s.wzz);
+          s.wxy = __builtin_fma(dx, p.fy, s.wxy);
+          s.wxz = __builtin_fma(dx, p.fz, s.wxz);
+          s.wyz = __builtin_fma(dy, p.fz, s.wyz);
+        }
+      }
+    }
+  }
+}
+
+template <bool MIXED, bool T1, bool EV, int U, bool SKIP>
 __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
   __shared__ double red[kForceWaves * 7];
-  Coef c1;
+  Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
   } else {
     load_table(a, tab);
   }
   const int32_t i = blockIdx.x * kForceThreads + threadIdx.x;
-  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
-  if (i < a.n) {
-    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
-                 zi = a.x[3 * (int64_t)i + 2];
+  Acc s;
+  const bool live = i < a.n;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = a.x[3 * (int64_t)i];
+    yi = a.x[3 * (int64_t)i + 1];
+    zi = a.x[3 * (int64_t)i + 2];
+  }
+  bool interior = false;
+  if constexpr (SKIP) {
+    const double m = a.rc;
+    const bool in = !live || (xi >= m && xi <= a.b.L[0] - m && yi >= m && yi <= a.b.L[1] - m &&
+                              zi >= m && zi <= a.b.L[2] - m);
+    interior = __ballot(!in) == 0;  // wavefront-uniform
+  }
+  if (live) {
     const int ti = T1 ? 0 : a.type[i];
     const int32_t cnt = a.nnbr[i];
     const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
-    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
-    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
-    for (int32_t k = 0; k < cnt; ++k) {
-      const int32_t j = row[(int64_t)k * kWave];
-      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
-      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
-      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
-      const double r2 = dist2(dx, dy, dz);
-      if (r2 < a.rc2) {
-        Coef c;
-        if constexpr (T1) {
-          c = c1;
-        } else {
-          const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
-          c = Coef{t[0], t[1], t[2], t[3]};
-        }
-        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
-        fx += p.fx;
-        fy += p.fy;
-        fz += p.fz;
-        if constexpr (EV) {
-          e += p.u;
-          wxx = __builtin_fma(dx, p.fx, wxx);
-          wyy = __builtin_fma(dy, p.fy, wyy);
-          wzz = __builtin_fma(dz, p.fz, wzz);
-          wxy = __builtin_fma(dx, p.fy, wxy);
-          wxz = __builtin_fma(dx, p.fz, wxz);
-          wyz = __builtin_fma(dy, p.fz, wyz);
-        }
-      }
-    }
-    a.F[3 * (int64_t)i] = fx;
-    a.F[3 * (int64_t)i + 1] = fy;
-    a.F[3 * (int64_t)i + 2] = fz;
-    if (a.e_atom) a.e_atom[i] = 0.5 * e;
+    if (SKIP && interior)
+      walk_row<MIXED, T1, EV, U, false>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+    else
+      walk_row<MIXED, T1, EV, U, true>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+    a.F[3 * (int64_t)i] = s.fx;
+    a.F[3 * (int64_t)i + 1] = s.fy;
+    a.F[3 * (int64_t)i + 2] = s.fz;
+    if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
   }
   if constexpr (EV) {
-    const double v[7] = {0.5 * e, 0.5 * wxx, 0.5 * wyy, 0.5 * wzz, 0.5 * wxy, 0.5 * wxz, 0.5 * wyz};
+    const double v[7] = {0.5 * s.e,   0.5 * s.wxx, 0.5 * s.wyy, 0.5 * s.wzz,
+                         0.5 * s.wxy, 0.5 * s.wxz, 0.5 * s.wyz};
     block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
   }
 }
@@ -237,12 +293,31 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
   }
 }
 
+// Loop-shape knobs of the full-list kernel, for tuning runs: LJMD_FORCE_UNROLL
+// (1, 2, 4) and LJMD_FORCE_INTERIOR (0/1).  Both shapes compute identical
+// results; the defaults are the measured best on MI355X.
+inline int knob(const char *name, int dflt) {
+  const char *v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
+
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
-  if (kind == LJMD_HALF)
+  if (kind == LJMD_HALF) {
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
-  else
-    k_force_full<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
+    return;
+  }
+  const int u = knob("LJMD_FORCE_UNROLL", 2);
+  const bool skip = knob("LJMD_FORCE_INTERIOR", 1) != 0;
+#define LJMD_FULL(U, S) k_force_full<MIXED, T1, EV, U, S><<<nblk, kForceThreads, 0, st>>>(a)
+  if (u >= 4) {
+    if (skip) LJMD_FULL(4, true); else LJMD_FULL(4, false);
+  } else if (u == 2) {
+    if (skip) LJMD_FULL(2, true); else LJMD_FULL(2, false);
+  } else {
+    if (skip) LJMD_FULL(1, true); else LJMD_FULL(1, false);
+  }
+#undef LJMD_FULL
 }
 
 template <bool MIXED>
@@ -269,6 +344,7 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
                   double *F, double *e_atom, double *ev, void *ws, hipStream_t st) {
   ForceArgs a;
   a.b = b;
+  a.rc = rc;
   a.rc2 = rc * rc;
   a.ntypes = ntypes;
   a.eps = eps;

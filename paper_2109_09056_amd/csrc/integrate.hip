@@ -134,7 +134,9 @@ int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n
   const double hdt = 0.5 * dt;
   const int unit = mass == 1.0;
   double *partial = (double *)ws;
-  if (stage == LJMD_KICK_DRIFT) {
+  if (stage == LJMD_KINETIC) {
+    k_sumsq_v<<<nb, kThreads, 0, st>>>(m3, v, partial);
+  } else if (stage == LJMD_KICK_DRIFT) {
     if (n > 0) k_kick_drift<<<nb, kThreads, 0, st>>>(m3, hdt, dt, mass, unit, b, x, v, F);
     if (ke) k_sumsq_v<<<nb, kThreads, 0, st>>>(m3, v, partial);
   } else {

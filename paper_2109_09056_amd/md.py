@@ -16,12 +16,13 @@ Velocity Verlet with a fixed rebuild cadence (no displacement check):
 """
 from __future__ import annotations
 
+import ctypes
 import math
 
 import torch
 
-from . import ops
-from ._lib import FP64, FULL, HALF, KICK, KICK_DRIFT
+from . import _lib, ops
+from ._lib import FP64, FULL, HALF, KICK, KICK_DRIFT, KINETIC
 
 
 def _dev(device):
@@ -100,6 +101,8 @@ class LJSim:
         self.dt = float(dt)
         self.mass = float(mass)
         self.rebuild_every = int(rebuild_every)
+        self.ntypes = ops._ntypes(self.eps)
+        self._box = _lib.make_box(self.L)
         self.nl = NeighborList(self.L, self.rlist, kind, device=self.device)
         self.step_count = 0
         self._ws = {}
@@ -128,6 +131,8 @@ class LJSim:
                                        device=dev)
         self.rebuild()
         self.compute_forces(energy=True)
+        ops.integrate(KINETIC, self.dt, self.mass, self.L, None, self.v, None, ke=self.ke,
+                      ws=self._ws[ops.OP_INTEGRATE])
         return self
 
     def rebuild(self):
@@ -147,28 +152,48 @@ class LJSim:
                            ev=self.ev if energy else None, want_energy=energy,
                            ws=self._ws[ops.OP_FORCES])
 
+    def _step_args(self, energy):
+        """ctypes argument tuples of the three per-step calls for the current buffers."""
+        p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        box = ctypes.byref(self._box)
+        n = self.n
+        wsf, wsi = self._ws[ops.OP_FORCES], self._ws[ops.OP_INTEGRATE]
+        kd = (KICK_DRIFT, self.dt, self.mass, box, n, p(self.x), p(self.v), p(self.F), None, None,
+              0, st)
+        fc = (box, self.precision, self.kind, self.rc, self.ntypes, p(self.eps), p(self.sigma), n,
+              p(self.x), p(self.types), p(self.nl.nbr), p(self.nl.nnbr), self.nl.maxn, p(self.F),
+              p(self.e_atom) if energy else None, p(self.ev) if energy else None, p(wsf),
+              wsf.numel(), st)
+        kk = (KICK, self.dt, self.mass, box, n, p(self.x), p(self.v), p(self.F),
+              p(self.ke) if energy else None, p(wsi), wsi.numel(), st)
+        return kd, fc, kk
+
     def step(self, nsteps=1, energy=True, force_timer=None):
         """Advance nsteps velocity-Verlet steps; energy: E, W and KE every step.
 
         force_timer: optional list receiving (start, end) timing events recorded on the
         current stream around every force call.
         """
+        lib = _lib.load()
+        integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
+        kd, fc, kk = self._step_args(energy)
         for _ in range(nsteps):
-            ops.integrate(KICK_DRIFT, self.dt, self.mass, self.L, self.x, self.v, self.F)
+            _lib.check(integrate(*kd), "ljmd_integrate")
             self.step_count += 1
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
+                kd, fc, kk = self._step_args(energy)
             if force_timer is not None:
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record()
-                self.compute_forces(energy)
+                _lib.check(forces(*fc), "ljmd_compute_forces")
                 b.record()
                 force_timer.append((a, b))
             else:
-                self.compute_forces(energy)
-            ops.integrate(KICK, self.dt, self.mass, self.L, self.x, self.v, self.F,
-                          ke=self.ke if energy else None, ws=self._ws[ops.OP_INTEGRATE])
+                _lib.check(forces(*fc), "ljmd_compute_forces")
+            _lib.check(integrate(*kk), "ljmd_integrate")
         return self
 
     # ---------------------------------------------------------------- reports

@@ -14,6 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
+                   KINETIC,
                    MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_FORCES, OP_INTEGRATE, OP_LOSS,
                    TILE, LjmdError, make_box)
 
@@ -154,8 +155,10 @@ def integrate(stage, dt, mass, L, x, v, F, ke=None, ws=None):
     n = v.shape[0]
     dev = v.device
     _need(v, "v", torch.float64, (n, 3))
-    _need(F, "F", torch.float64, (n, 3), dev)
-    _need(x, "x", torch.float64, (n, 3), dev)
+    if stage != KINETIC or F is not None:
+        _need(F, "F", torch.float64, (n, 3), dev)
+    if stage != KINETIC or x is not None:
+        _need(x, "x", torch.float64, (n, 3), dev)
     _need(ke, "ke", torch.float64, (1,), dev)
     need = 0
     if ke is not None:
