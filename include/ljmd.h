@@ -63,6 +63,9 @@ extern "C" {
 #define LJMD_KICK_DRIFT 0 /* v += dt/2 F/m; x += dt v; wrap x into [0, L) */
 #define LJMD_KICK 1       /* v += dt/2 F/m */
 #define LJMD_KINETIC 2    /* no update: only the kinetic energy 1/2 m sum v^2 into ke */
+#define LJMD_KICK_KICK_DRIFT 3 /* end of one step and start of the next, one pass:
+                                  v += dt/2 F/m (ke taken here); v += dt/2 F/m;
+                                  x += dt v; wrap -- bitwise equal to KICK then KICK_DRIFT */
 
 /* workspace queries (ljmd_workspace_bytes) */
 #define LJMD_OP_BIN 0
@@ -183,6 +186,9 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
  *   stage LJMD_KICK:       v += dt/2 F/m
  *   stage LJMD_KINETIC:    nothing is updated (x, F may be NULL, dt is ignored);
  *                          ke is required
+ *   stage LJMD_KICK_KICK_DRIFT: LJMD_KICK followed by LJMD_KICK_DRIFT with the
+ *                          same F, in one pass; ke (if given) is the kinetic
+ *                          energy between the two kicks (the integer time step)
  *   ke    device FP64 scalar receiving 1/2 m sum v^2 after the update, or NULL
  *   ws    >= ljmd_workspace_bytes(LJMD_OP_INTEGRATE, n, 0, 0) when ke != NULL
  */

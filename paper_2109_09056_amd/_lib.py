@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libljmd.so")
 OK, EINVAL, EBOX, EWORKSPACE, EHIP = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 FULL, HALF = 0, 1
-KICK_DRIFT, KICK, KINETIC = 0, 1, 2
+KICK_DRIFT, KICK, KINETIC, KICK_KICK_DRIFT = 0, 1, 2, 3
 OP_BIN, OP_FORCES, OP_BACKWARD, OP_INTEGRATE, OP_LOSS = 0, 1, 2, 3, 4
 MAX_TYPES = 8
 TILE = 64

@@ -234,7 +234,8 @@ int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64
                    double *x, double *v, const double *F, double *ke, void *ws,
                    size_t ws_bytes, void *stream) {
   LJMD_TRY(check_n(n));
-  if (stage != LJMD_KICK_DRIFT && stage != LJMD_KICK && stage != LJMD_KINETIC)
+  if (stage != LJMD_KICK_DRIFT && stage != LJMD_KICK && stage != LJMD_KINETIC &&
+      stage != LJMD_KICK_KICK_DRIFT)
     return set_error(LJMD_EINVAL, "bad stage %d", stage);
   if (stage == LJMD_KINETIC) {
     if (!ke) return set_error(LJMD_EINVAL, "ke is NULL for the kinetic-energy stage");
@@ -243,11 +244,12 @@ int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64
     return set_error(LJMD_EINVAL, "dt = %g", dt);
   }
   if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g", mass);
-  if (stage == LJMD_KICK_DRIFT) LJMD_TRY(check_box(box));
-  if (n > 0 && stage != LJMD_KINETIC && (!v || !F || (stage == LJMD_KICK_DRIFT && !x)))
+  const bool drift = stage == LJMD_KICK_DRIFT || stage == LJMD_KICK_KICK_DRIFT;
+  if (drift) LJMD_TRY(check_box(box));
+  if (n > 0 && stage != LJMD_KINETIC && (!v || !F || (drift && !x)))
     return set_error(LJMD_EINVAL, "x/v/F is NULL");
   if (ke) LJMD_TRY(check_ws(ws, ws_bytes, stream_workspace(n)));
-  BoxK b = stage == LJMD_KICK_DRIFT ? make_box(box) : BoxK{};
+  BoxK b = drift ? make_box(box) : BoxK{};
   return launch_integrate(stage, dt, mass, b, n, x, v, F, ke, ws, (hipStream_t)stream);
 }
 

@@ -3,14 +3,15 @@
 // re-sort that begins each MD timestep (Introduction).
 //
 // Four launches:
-//   1. cell id + histogram   one thread per atom, atomic count per cell
-//   2. exclusive scan        one 1024-thread block over all cells
-//   3. scatter               one thread per atom claims a slot in its cell
+//   1. cell id + histogram   one thread per atom; lanes of a wavefront in the
+//                            same cell share one atomic add and get ranks
+//   2. exclusive scan        one 1024-thread block over all cells, in chunks
+//   3. scatter               one thread per atom to slot start[cell] + rank
 //   4. in-cell rank + permute  one wavefront per cell: ids of the cell are
 //                            staged in LDS, each lane ranks its atom among
 //                            them, then copies x, v, type, id to the ranked slot.
-// Step 3's slot order depends on atomic timing; step 4 replaces it by the id
-// order, so the output permutation is deterministic.
+// The rank order of step 1 depends on atomic timing; step 4 replaces it by
+// the id order, so the output permutation is deterministic.
 #include "common.h"
 
 namespace ljmd {
@@ -37,51 +38,89 @@ __global__ void k_fill_i32(int32_t *p, int64_t m, int32_t val) {
   if (i < m) p[i] = val;
 }
 
+// Cell of every atom and its rank among the atoms of its cell that were
+// counted before it.  Lanes of a wavefront that fall in the same cell (the
+// common case: the input is usually the previous sorted order) are grouped by
+// a ballot loop, and each group's leader makes one atomic add for the group.
 __global__ void k_count(int64_t n, const double *__restrict__ x, GridK g,
-                        int32_t *__restrict__ cell, int32_t *__restrict__ counts) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t c = cell_of(x + 3 * i, g);
-  cell[i] = c;
-  atomicAdd(&counts[c], 1);
+                        int32_t *__restrict__ cell, int32_t *__restrict__ rank,
+                        int32_t *__restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < n;
+  const int32_t c = live ? cell_of(x + 3 * i, g) : -1;
+  const int lane = threadIdx.x & (kWave - 1);
+  bool pending = live;
+  int32_t r = 0;
+  while (__ballot(pending) != 0) {
+    const uint64_t act = __ballot(pending);
+    const int leader = __builtin_ctzll(act);
+    const int32_t lc = __shfl(c, leader, kWave);
+    const bool mine = pending && c == lc;
+    const uint64_t grp = __ballot(mine);
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[lc], (int32_t)__popcll(grp));
+    base = __shfl(base, leader, kWave);
+    if (mine) {
+      r = base + (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+      pending = false;
+    }
+  }
+  if (live) {
+    cell[i] = c;
+    rank[i] = r;
+  }
 }
 
-// Exclusive scan of counts[0..m) into start[0..m] (start[m] = total) and a
-// copy into cursor[0..m).  One block; each thread owns a contiguous run.
+// Exclusive scan of counts[0..m) into start[0..m] (start[m] = total).  One
+// block walks the cells in chunks of 4 * kScanThreads: coalesced loads, a
+// block scan in LDS, and a running carry between chunks.
 __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t m, const int32_t *__restrict__ counts,
-                                                     int32_t *__restrict__ start,
-                                                     int32_t *__restrict__ cursor) {
+                                                     int32_t *__restrict__ start) {
   __shared__ int32_t part[kScanThreads];
+  __shared__ int32_t carry_s;
   const int t = threadIdx.x;
-  const int32_t per = (m + kScanThreads - 1) / kScanThreads;
-  const int32_t lo = t * per;
-  const int32_t hi = lo + per < m ? lo + per : m;
-  int32_t s = 0;
-  for (int32_t c = lo; c < hi; ++c) s += counts[c];
-  part[t] = s;
+  if (t == 0) carry_s = 0;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread sums
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int32_t v = t >= off ? part[t - off] : 0;
+  for (int32_t c0 = 0; c0 < m; c0 += 4 * kScanThreads) {
+    int32_t v[4];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t c = c0 + 4 * t + q;
+      v[q] = c < m ? counts[c] : 0;
+      s += v[q];
+    }
+    part[t] = s;
     __syncthreads();
-    part[t] += v;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const int32_t o = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += o;
+      __syncthreads();
+    }
+    const int32_t carry = carry_s;
+    int32_t run = carry + part[t] - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t c = c0 + 4 * t + q;
+      if (c < m) start[c] = run;
+      run += v[q];
+    }
+    __syncthreads();
+    if (t == kScanThreads - 1) carry_s = carry + part[t];
     __syncthreads();
   }
-  int32_t run = part[t] - s;
-  for (int32_t c = lo; c < hi; ++c) {
-    start[c] = run;
-    cursor[c] = run;
-    run += counts[c];
-  }
-  if (t == kScanThreads - 1) start[m] = part[t];
+  if (t == 0) start[m] = carry_s;
 }
 
-__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell, int32_t *__restrict__ cursor,
+// Slot of atom i: start of its cell plus its rank (no atomics).
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell,
+                          const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
                           int32_t *__restrict__ src) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t pos = atomicAdd(&cursor[cell[i]], 1);
-  src[pos] = (int32_t)i;
+  src[start[cell[i]] + rank[i]] = (int32_t)i;
 }
 
 __device__ __forceinline__ int64_t id_at(const int64_t *id_in, int32_t s) {
@@ -140,9 +179,9 @@ inline unsigned blocks_for(int64_t n, int threads) {
 }  // namespace
 
 size_t bin_workspace(int64_t n, int64_t ncells) {
-  // counts[ncells] + cursor[ncells] + cell[n] + src[n], int32, 256-byte aligned
+  // counts[ncells] + cell[n] + rank[n] + src[n], int32, 256-byte aligned
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return 2 * al((size_t)ncells * 4) + 2 * al((size_t)n * 4);
+  return al((size_t)ncells * 4) + 3 * al((size_t)n * 4);
 }
 
 int launch_bin(const GridK &g, int64_t n, const double *x_in, const double *v_in,
@@ -153,17 +192,17 @@ int launch_bin(const GridK &g, int64_t n, const double *x_in, const double *v_in
   char *p = (char *)ws;
   int32_t *counts = (int32_t *)p;
   p += al((size_t)g.ncells * 4);
-  int32_t *cursor = (int32_t *)p;
-  p += al((size_t)g.ncells * 4);
   int32_t *cell = (int32_t *)p;
+  p += al((size_t)n * 4);
+  int32_t *rank = (int32_t *)p;
   p += al((size_t)n * 4);
   int32_t *src = (int32_t *)p;
 
   k_fill_i32<<<blocks_for(g.ncells, 256), 256, 0, st>>>(counts, g.ncells, 0);
-  if (n > 0) k_count<<<blocks_for(n, 256), 256, 0, st>>>(n, x_in, g, cell, counts);
-  k_scan<<<1, kScanThreads, 0, st>>>(g.ncells, counts, cell_start, cursor);
+  if (n > 0) k_count<<<blocks_for(n, 256), 256, 0, st>>>(n, x_in, g, cell, rank, counts);
+  k_scan<<<1, kScanThreads, 0, st>>>(g.ncells, counts, cell_start);
   if (n > 0) {
-    k_scatter<<<blocks_for(n, 256), 256, 0, st>>>(n, cell, cursor, src);
+    k_scatter<<<blocks_for(n, 256), 256, 0, st>>>(n, cell, rank, cell_start, src);
     k_permute<<<blocks_for(g.ncells, kPermWaves), kPermWaves * kWave, 0, st>>>(
         g.ncells, cell_start, src, x_in, v_in, type_in, id_in, x_out, v_out, type_out, id_out);
   }

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
 }
 
 // Loop-shape knobs of the full-list kernel, for tuning runs: LJMD_FORCE_UNROLL
-// (1, 2, 4) and LJMD_FORCE_INTERIOR (0/1).  Both shapes compute identical
+// (1, 2, 4, 8) and LJMD_FORCE_INTERIOR (0/1).  Both shapes compute identical
 // results; the defaults are the measured best on MI355X.
 inline int knob(const char *name, int dflt) {
   const char *v = getenv(name);
@@ -307,10 +307,12 @@ void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
     return;
   }
-  const int u = knob("LJMD_FORCE_UNROLL", 2);
+  const int u = knob("LJMD_FORCE_UNROLL", 4);
   const bool skip = knob("LJMD_FORCE_INTERIOR", 1) != 0;
 #define LJMD_FULL(U, S) k_force_full<MIXED, T1, EV, U, S><<<nblk, kForceThreads, 0, st>>>(a)
-  if (u >= 4) {
+  if (u >= 8) {
+    if (skip) LJMD_FULL(8, true); else LJMD_FULL(8, false);
+  } else if (u >= 4) {
     if (skip) LJMD_FULL(4, true); else LJMD_FULL(4, false);
   } else if (u == 2) {
     if (skip) LJMD_FULL(2, true); else LJMD_FULL(2, false);

@@ -35,6 +35,39 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(int64_t m3, double hdt,
   x[q] = xq;
 }
 
+// End-of-step half kick, kinetic energy, then the next step's half kick,
+// drift and wrap: the same operations as k_kick followed by k_kick_drift.
+template <bool KE>
+__global__ __launch_bounds__(kThreads) void k_kick_kick_drift(int64_t m3, double hdt, double dt,
+                                                              double mass, int unit_mass, BoxK b,
+                                                              double *__restrict__ x,
+                                                              double *__restrict__ v,
+                                                              const double *__restrict__ F,
+                                                              double *__restrict__ partial) {
+  __shared__ double red[kThreads / kWave];
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double vv = 0.0;
+  if (q < m3) {
+    const int k = (int)(q % 3);
+    const double L = k == 0 ? b.L[0] : (k == 1 ? b.L[1] : b.L[2]);
+    double kick = hdt * F[q];
+    if (!unit_mass) kick = kick / mass;
+    const double vn = v[q] + kick;
+    vv = vn * vn;
+    const double vh = vn + kick;
+    double xq = x[q] + dt * vh;
+    if (xq >= L) xq -= L;
+    else if (xq < 0.0) xq += L;
+    if (xq >= L) xq -= L;
+    v[q] = vh;
+    x[q] = xq;
+  }
+  if constexpr (KE) {
+    const double s[1] = {vv};
+    block_sum<kThreads / kWave, 1>(s, red, partial + blockIdx.x);
+  }
+}
+
 template <bool KE>
 __global__ __launch_bounds__(kThreads) void k_kick(int64_t m3, double hdt, double mass,
                                                    int unit_mass, double *__restrict__ v,
@@ -136,6 +169,13 @@ int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n
   double *partial = (double *)ws;
   if (stage == LJMD_KINETIC) {
     k_sumsq_v<<<nb, kThreads, 0, st>>>(m3, v, partial);
+  } else if (stage == LJMD_KICK_KICK_DRIFT) {
+    if (ke)
+      k_kick_kick_drift<true><<<nb, kThreads, 0, st>>>(m3, hdt, dt, mass, unit, b, x, v, F,
+                                                       partial);
+    else if (n > 0)
+      k_kick_kick_drift<false><<<nb, kThreads, 0, st>>>(m3, hdt, dt, mass, unit, b, x, v, F,
+                                                        partial);
   } else if (stage == LJMD_KICK_DRIFT) {
     if (n > 0) k_kick_drift<<<nb, kThreads, 0, st>>>(m3, hdt, dt, mass, unit, b, x, v, F);
     if (ke) k_sumsq_v<<<nb, kThreads, 0, st>>>(m3, v, partial);

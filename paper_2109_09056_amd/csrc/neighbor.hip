@@ -76,6 +76,61 @@ __device__ __forceinline__ int32_t locate(int32_t t, const int32_t *rs, const in
   return rs[r] + (t - pre[r]);
 }
 
+// Register-staged build of one cell's rows (candidates <= kSlots * 64).
+template <bool HALF, bool WRAP>
+__device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const double *__restrict__ x,
+                                             int32_t h0, int32_t h1, int32_t total, int nslot,
+                                             const int32_t *rs, const int32_t *pre, int32_t maxn,
+                                             int32_t *__restrict__ nbr, int32_t *__restrict__ nnbr,
+                                             int32_t &maxc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
+  const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
+  double qx[kSlots], qy[kSlots], qz[kSlots];
+  int32_t qj[kSlots];
+#pragma unroll
+  for (int r = 0; r < kSlots; ++r) {
+    const int32_t t = r * kWave + lane;
+    qj[r] = -1;
+    qx[r] = qy[r] = qz[r] = 0.0;
+    if (r < nslot && t < total) {
+      const int32_t j = locate(t, rs, pre);
+      qj[r] = j;
+      qx[r] = x[3 * (int64_t)j];
+      qy[r] = x[3 * (int64_t)j + 1];
+      qz[r] = x[3 * (int64_t)j + 2];
+    }
+  }
+  for (int32_t i = h0; i < h1; ++i) {
+    const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
+    int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+    int32_t base = 0;
+#pragma unroll
+    for (int r = 0; r < kSlots; ++r) {
+      if (r < nslot) {
+        double dx = xi - qx[r], dy = yi - qy[r], dz = zi - qz[r];
+        if constexpr (WRAP) {
+          dx = min_image(dx, L0, iL0);
+          dy = min_image(dy, L1, iL1);
+          dz = min_image(dz, L2, iL2);
+        }
+        const double r2 = dist2(dx, dy, dz);
+        const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+          const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                                       (uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (k < maxn) row[(int64_t)k * kWave] = qj[r];
+        }
+        base += (int32_t)__popcll(m);
+      }
+    }
+    if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
+    maxc = base > maxc ? base : maxc;
+  }
+}
+
 template <bool HALF>
 __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
                                                  const double *__restrict__ x,
@@ -93,52 +148,25 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
   const int S = stencil_ranges(g, c, cell_start, rs, pre);
   const int32_t total = pre[S];
   const int nslot = (total + kWave - 1) / kWave;
-  const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
-  const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
   int32_t maxc = 0;
-
+  // A home cell whose stencil does not wrap (nc >= 4 and the cell is not on a
+  // face) pairs atoms at most two cell edges = L/2 apart per dimension: the raw
+  // displacement is then the minimum image for every pair that can be inside
+  // rlist, and any pair at ~L/2 is beyond rlist whichever image is taken.
+  bool wrap = false;
+  {
+    const int32_t cc[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+    for (int k = 0; k < 3; ++k)
+      wrap |= g.nc[k] < 4 || cc[k] == 0 || cc[k] == g.nc[k] - 1;
+  }
   if (nslot <= kSlots) {
-    double qx[kSlots], qy[kSlots], qz[kSlots];
-    int32_t qj[kSlots];
-#pragma unroll
-    for (int r = 0; r < kSlots; ++r) {
-      const int32_t t = r * kWave + lane;
-      qj[r] = -1;
-      qx[r] = qy[r] = qz[r] = 0.0;
-      if (r < nslot && t < total) {
-        const int32_t j = locate(t, rs, pre);
-        qj[r] = j;
-        qx[r] = x[3 * (int64_t)j];
-        qy[r] = x[3 * (int64_t)j + 1];
-        qz[r] = x[3 * (int64_t)j + 2];
-      }
-    }
-    for (int32_t i = h0; i < h1; ++i) {
-      const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
-      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
-      int32_t base = 0;
-#pragma unroll
-      for (int r = 0; r < kSlots; ++r) {
-        if (r < nslot) {
-          const double dx = min_image(xi - qx[r], L0, iL0);
-          const double dy = min_image(yi - qy[r], L1, iL1);
-          const double dz = min_image(zi - qz[r], L2, iL2);
-          const double r2 = dist2(dx, dy, dz);
-          const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
-          const uint64_t m = __ballot(ok);
-          if (ok) {
-            const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
-                                         (uint32_t)(m >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (k < maxn) row[(int64_t)k * kWave] = qj[r];
-          }
-          base += (int32_t)__popcll(m);
-        }
-      }
-      if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
-      maxc = base > maxc ? base : maxc;
-    }
+    if (wrap)
+      build_staged<HALF, true>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, maxc);
+    else
+      build_staged<HALF, false>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, maxc);
   } else {
+    const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
+    const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
     for (int32_t i = h0; i < h1; ++i) {
       const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
       int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));

@@ -13,6 +13,8 @@ Velocity Verlet with a fixed rebuild cadence (no displacement check):
     every `rebuild_every` steps: re-sort by cell and rebuild the list
     F = F(x)                                   (ljmd_compute_forces)
     v += dt/2 F/m                              (ljmd_integrate KICK)
+Inside one call the closing kick of a step and the opening kick + drift of
+the next run as one launch (ljmd_integrate KICK_KICK_DRIFT, bitwise equal).
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ import math
 import torch
 
 from . import _lib, ops
-from ._lib import FP64, FULL, HALF, KICK, KICK_DRIFT, KINETIC
+from ._lib import FP64, FULL, HALF, KICK, KICK_DRIFT, KICK_KICK_DRIFT, KINETIC
 
 
 def _dev(device):
@@ -167,7 +169,8 @@ class LJSim:
               wsf.numel(), st)
         kk = (KICK, self.dt, self.mass, box, n, p(self.x), p(self.v), p(self.F),
               p(self.ke) if energy else None, p(wsi), wsi.numel(), st)
-        return kd, fc, kk
+        kkd = (KICK_KICK_DRIFT,) + kk[1:]
+        return kd, fc, kk, kkd
 
     def step(self, nsteps=1, energy=True, force_timer=None):
         """Advance nsteps velocity-Verlet steps; energy: E, W and KE every step.
@@ -177,13 +180,15 @@ class LJSim:
         """
         lib = _lib.load()
         integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
-        kd, fc, kk = self._step_args(energy)
-        for _ in range(nsteps):
-            _lib.check(integrate(*kd), "ljmd_integrate")
+        if nsteps <= 0:
+            return self
+        kd, fc, kk, kkd = self._step_args(energy)
+        _lib.check(integrate(*kd), "ljmd_integrate")
+        for s in range(nsteps):
             self.step_count += 1
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
-                kd, fc, kk = self._step_args(energy)
+                kd, fc, kk, kkd = self._step_args(energy)
             if force_timer is not None:
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
@@ -193,7 +198,9 @@ class LJSim:
                 force_timer.append((a, b))
             else:
                 _lib.check(forces(*fc), "ljmd_compute_forces")
-            _lib.check(integrate(*kk), "ljmd_integrate")
+            # closing half kick of this step fused with the opening kick + drift of the
+            # next one (same operations, one pass); the call ends on a plain half kick
+            _lib.check(integrate(*(kk if s == nsteps - 1 else kkd)), "ljmd_integrate")
         return self
 
     # ---------------------------------------------------------------- reports

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
-                   KINETIC,
+                   KICK_KICK_DRIFT, KINETIC,
                    MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_FORCES, OP_INTEGRATE, OP_LOSS,
                    TILE, LjmdError, make_box)
 

@@ -103,7 +103,7 @@ def test_validation_rejects_bad_arguments(lib):
     assert call(lib, "ljmd_compute_forces", bb, 0, 0, 2.5, 1, fake, fake, 10, fake, None, fake,
                 fake, 8, fake, fake, fake, None, 0, None) == lib.EWORKSPACE
     # integrate: bad stage, zero dt, bad mass
-    assert call(lib, "ljmd_integrate", 3, 0.005, 1.0, bb, 10, fake, fake, fake, None, None, 0,
+    assert call(lib, "ljmd_integrate", 7, 0.005, 1.0, bb, 10, fake, fake, fake, None, None, 0,
                 None) == lib.EINVAL
     assert call(lib, "ljmd_integrate", 0, 0.0, 1.0, bb, 10, fake, fake, fake, None, None, 0,
                 None) == lib.EINVAL
