@@ -38,7 +38,8 @@ struct BwdArgs {
   const double *g;
   double *gx;
   int accumulate;
-  double *partial;  // [nblk][2 T T]: (eps | sigma) x (type of i) x (type of j)
+  int stride;       // partial row length: 2 T T rounded up to a power of two
+  double *partial;  // [nblk][stride]: (eps | sigma) x (type of i) x (type of j), then padding
 };
 
 // sigma^2, 48 eps, 24 eps, -336 eps, 96 eps, 576 eps/sigma, 144 eps/sigma
@@ -120,13 +121,29 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
     const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
     const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int32_t k = 0; k < cnt; ++k) {
-      const int32_t j = row[(int64_t)k * kWave];
-      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
-      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
-      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
+    // U slots per iteration: all index loads, then all gathers of x_j and g_j,
+    // then the U pair evaluations (several loads in flight per lane).
+    constexpr int U = 4;
+    for (int32_t k0 = 0; k0 < cnt; k0 += U) {
+      int32_t jj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) jj[u] = row[(int64_t)((u == 0 || k0 + u < cnt) ? k0 + u : k0) * kWave];
+      double xj[U][3], gj[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          xj[u][q] = a.x[3 * (int64_t)jj[u] + q];
+          gj[u][q] = a.g[3 * (int64_t)jj[u] + q];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+      const int32_t j = jj[u];
+      const double dx = min_image(xi - xj[u][0], L0, iL0);
+      const double dy = min_image(yi - xj[u][1], L1, iL1);
+      const double dz = min_image(zi - xj[u][2], L2, iL2);
       const double r2 = dist2(dx, dy, dz);
-      if (r2 < a.rc2) {
+      if ((u == 0 || k0 + u < cnt) && r2 < a.rc2) {
         int tj = 0;
         BCoef c;
         if constexpr (TT == 1) {
@@ -137,9 +154,9 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
           c = BCoef{t[0], t[1], t[2], t[3], t[4], t[5], t[6]};
         }
         const PairB p = pair_b<MIXED>(r2, c);
-        const double dgx = gxi - a.g[3 * (int64_t)j];
-        const double dgy = gyi - a.g[3 * (int64_t)j + 1];
-        const double dgz = gzi - a.g[3 * (int64_t)j + 2];
+        const double dgx = gxi - gj[u][0];
+        const double dgy = gyi - gj[u][1];
+        const double dgz = gzi - gj[u][2];
         const double ddg = __builtin_fma(dx, dgx, __builtin_fma(dy, dgy, dz * dgz));
         const double q = 2.0 * p.sp * ddg;
         ax = __builtin_fma(p.s, dgx, __builtin_fma(q, dx, ax));
@@ -164,6 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
           col[MT + tj] = __builtin_fma(gid, p.dss, col[MT + tj]);
         }
       }
+      }
     }
     double *o = a.gx + 3 * (int64_t)i;
     if (a.accumulate) {
@@ -177,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
     }
   }
   // per-block sums G[which][ti][tj] in a fixed order
-  double *out = a.partial + (int64_t)blockIdx.x * 2 * T * T;
+  double *out = a.partial + (int64_t)blockIdx.x * a.stride;
   if constexpr (TT == 1) {
     const double v[2] = {ge[0], gs[0]};
     block_sum<kWaves, 2>(v, red, out);
@@ -232,9 +250,14 @@ unsigned bwd_blocks(int64_t n) {
   return (unsigned)(b > 0 ? b : 1);
 }
 
+static int partial_stride(int32_t ntypes) {
+  int s = 1;
+  while (s < 2 * ntypes * ntypes) s <<= 1;
+  return s;
+}
+
 size_t bwd_workspace(int64_t n, int32_t ntypes) {
-  const size_t cols = 2 * (size_t)ntypes * ntypes;
-  return ((size_t)bwd_blocks(n) + 1) * cols * sizeof(double);
+  return ((size_t)bwd_blocks(n) + 1) * partial_stride(ntypes) * sizeof(double);
 }
 
 int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
@@ -257,10 +280,12 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
   a.g = g;
   a.gx = gx;
   a.accumulate = accumulate;
+  a.stride = partial_stride(ntypes);
   a.partial = (double *)ws;
   const unsigned nblk = bwd_blocks(n);
   const int cols = 2 * ntypes * ntypes;
-  double *colsums = a.partial + (size_t)nblk * cols;
+  const int stride = a.stride;
+  double *colsums = a.partial + (size_t)nblk * stride;
   const bool mixed = precision == LJMD_MIXED;
 #define LJMD_VJP(M, TT) k_vjp<M, TT><<<nblk, kThreads, 0, st>>>(a)
   if (ntypes == 1) {
@@ -271,7 +296,7 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
     if (mixed) LJMD_VJP(true, 0); else LJMD_VJP(false, 0);
   }
 #undef LJMD_VJP
-  k_colsum<256><<<cols, 256, 0, st>>>(nblk, cols, a.partial, colsums, 1.0, 0);
+  k_colsum<256><<<1, 256, 0, st>>>(nblk, stride, cols, a.partial, colsums, 1.0, 0);
   k_param_finalize<<<1, 128, 0, st>>>(ntypes, colsums, geps, gsig, accumulate);
   return check_launch("ljmd_force_backward");
 }

@@ -90,22 +90,28 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double *red, do
   }
 }
 
-// Column sums over `rows` partial rows of `stride` doubles, one block per
-// column q:  out[q] = scale * sum_r p[r*stride + q]  (+= when accumulate),
-// summed in a fixed order.
+// Column sums over `rows` partial rows of `stride` doubles (stride divides
+// THREADS), one block:  out[q] = scale * sum_r p[r*stride + q] for q < ncols
+// (+= when accumulate).  Thread t reads the flat array at t, t + THREADS, ...
+// (coalesced), so it always sees column t % stride; the THREADS/stride
+// threads of a column are then added in thread order.  Fixed order throughout.
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride,
+__global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, int ncols,
                                                    const double *__restrict__ p,
                                                    double *__restrict__ out, double scale,
                                                    int accumulate) {
-  __shared__ double red[THREADS / kWave];
-  __shared__ double tot[1];
-  const int q = blockIdx.x;
+  __shared__ double part[THREADS];
+  const int t = threadIdx.x;
   double s = 0.0;
-  for (int64_t r = threadIdx.x; r < rows; r += THREADS) s += p[r * stride + q];
-  const double v[1] = {s};
-  block_sum<THREADS / kWave, 1>(v, red, tot);
-  if (threadIdx.x == 0) out[q] = accumulate ? out[q] + scale * tot[0] : scale * tot[0];
+  const int64_t total = rows * stride;
+  for (int64_t f = t; f < total; f += THREADS) s += p[f];
+  part[t] = s;
+  __syncthreads();
+  if (t < ncols) {
+    double tot = 0.0;
+    for (int k = t; k < THREADS; k += stride) tot += part[k];
+    out[t] = accumulate ? out[t] + scale * tot : scale * tot;
+  }
 }
 
 // Packed upper-triangle index of the type pair (a, b).

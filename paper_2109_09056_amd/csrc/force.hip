@@ -307,7 +307,7 @@ void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
     return;
   }
-  const int u = knob("LJMD_FORCE_UNROLL", 4);
+  const int u = knob("LJMD_FORCE_UNROLL", 8);
   const bool skip = knob("LJMD_FORCE_INTERIOR", 1) != 0;
 #define LJMD_FULL(U, S) k_force_full<MIXED, T1, EV, U, S><<<nblk, kForceThreads, 0, st>>>(a)
   if (u >= 8) {
@@ -374,7 +374,7 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   } else if (ev) {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
   }
-  if (ev) k_colsum<256><<<7, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, a.partial, ev, 1.0, 0);
+  if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces");
 }
 

@@ -28,35 +28,49 @@ __device__ __forceinline__ int stencil_ranges(const GridK &g, int32_t c, const i
                                               int32_t *rs, int32_t *pre) {
   const int lane = threadIdx.x & (kWave - 1);
   int32_t cc[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
-  int32_t cells[3][3];
-  int cnt[3];
+  // y and z: the distinct cells among c-1, c, c+1 (mod nc)
+  int32_t cells[2][3];
+  int cnt[2];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 1; k < 3; ++k) {
     const int32_t m = g.nc[k];
     if (m >= 3) {
-      cells[k][0] = cc[k] == 0 ? m - 1 : cc[k] - 1;
-      cells[k][1] = cc[k];
-      cells[k][2] = cc[k] == m - 1 ? 0 : cc[k] + 1;
-      cnt[k] = 3;
+      cells[k - 1][0] = cc[k] == 0 ? m - 1 : cc[k] - 1;
+      cells[k - 1][1] = cc[k];
+      cells[k - 1][2] = cc[k] == m - 1 ? 0 : cc[k] + 1;
+      cnt[k - 1] = 3;
     } else {
-      cells[k][0] = 0;
-      cells[k][1] = 1;
-      cells[k][2] = 0;
-      cnt[k] = m;
+      cells[k - 1][0] = 0;
+      cells[k - 1][1] = 1;
+      cells[k - 1][2] = 0;
+      cnt[k - 1] = m;
     }
   }
-  const int S = cnt[0] * cnt[1] * cnt[2];
+  // x: runs of consecutive cells, which are consecutive in sorted order too
+  const int32_t mx = g.nc[0];
+  int32_t run0[2], runlen[2];
+  int nrun;
+  if (mx < 3) {
+    run0[0] = 0, runlen[0] = mx, nrun = 1;
+  } else if (cc[0] == 0) {
+    run0[0] = 0, runlen[0] = 2, run0[1] = mx - 1, runlen[1] = 1, nrun = 2;
+  } else if (cc[0] == mx - 1) {
+    run0[0] = mx - 2, runlen[0] = 2, run0[1] = 0, runlen[1] = 1, nrun = 2;
+  } else {
+    run0[0] = cc[0] - 1, runlen[0] = 3, nrun = 1;
+  }
+  const int S = nrun * cnt[0] * cnt[1];
   int32_t len = 0;
   if (lane < S) {
-    const int ix = lane % cnt[0];
-    const int iy = (lane / cnt[0]) % cnt[1];
-    const int iz = lane / (cnt[0] * cnt[1]);
-    const int32_t s = (cells[2][iz] * g.nc[1] + cells[1][iy]) * g.nc[0] + cells[0][ix];
-    const int32_t a = cell_start[s];
+    const int ir = lane % nrun;
+    const int iy = (lane / nrun) % cnt[0];
+    const int iz = lane / (nrun * cnt[0]);
+    const int32_t row = (cells[1][iz] * g.nc[1] + cells[0][iy]) * mx;
+    const int32_t a = cell_start[row + run0[ir]];
     rs[lane] = a;
-    len = cell_start[s + 1] - a;
+    len = cell_start[row + run0[ir] + runlen[ir]] - a;
   }
-  // inclusive prefix of len over the first S lanes (S <= 27 < 32)
+  // inclusive prefix of len over the first S lanes (S <= 18 < 32)
   int32_t inc = len;
 #pragma unroll
   for (int off = 1; off < 32; off <<= 1) {

@@ -56,6 +56,27 @@ def test_force_vjp_vs_oracle(dev, orc, fm, prec):
     assert ex <= tol and ee <= tol and es <= tol
 
 
+def test_force_vjp_three_types(dev, orc):
+    """General type count (per-lane LDS accumulators): 256 atoms, three types."""
+    from paper_2109_09056_amd import autograd, ops
+    w = li.WORKLOADS["lj256"]
+    x = li.positions(w)
+    ty = (np.arange(w.natoms) % 3).astype(np.int32)
+    eps = np.array([1.0, 0.9, 1.1, 1.2, 0.8, 1.05])
+    sig = np.array([1.0, 0.95, 1.02, 1.05, 0.92, 0.97])
+    g = np.random.default_rng(9).normal(size=x.shape)
+    lst = orc.neighbor_lists(x, w.box, w.rlist)
+    gxo, geo, gso = orc.force_vjp(x, w.box, w.rc, g, eps, sig, ty, *lst)
+    fc = autograd.ForceContext(w.box, x, ty, rc=w.rc, skin=w.skin, device=dev)
+    for prec, tol in ((ops.FP64, 1e-12), (ops.MIXED, 1e-4)):
+        gx, ge, gs = ops.force_backward(w.box, prec, w.rc, T(eps, dev), T(sig, dev), fc.x,
+                                        fc.types, fc.nl.nbr, fc.nl.nnbr, fc.nl.maxn,
+                                        fc.sorted_rows(g))
+        assert max_rel_vec(fc.caller_rows(gx).cpu().numpy(), gxo) <= tol
+        assert np.abs(ge.cpu().numpy() - geo).max() <= tol * np.abs(geo).max()
+        assert np.abs(gs.cpu().numpy() - gso).max() <= tol * np.abs(gso).max()
+
+
 def test_force_vjp_accumulate_and_deterministic(dev, fm):
     import torch
     from paper_2109_09056_amd import ops
