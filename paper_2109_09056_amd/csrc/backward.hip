@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
   BCoef c1{};
   if constexpr (TT == 1) c1 = bcoef(a.eps, a.sig, 0);
 
-  const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double ge[TT == 0 ? 1 : TT], gs[TT == 0 ? 1 : TT];
 #pragma unroll
   for (int q = 0; q < (TT == 0 ? 1 : TT); ++q) ge[q] = gs[q] = 0.0;

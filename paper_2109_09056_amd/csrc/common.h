@@ -104,7 +104,17 @@ __global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, in
   const int t = threadIdx.x;
   double s = 0.0;
   const int64_t total = rows * stride;
-  for (int64_t f = t; f < total; f += THREADS) s += p[f];
+  constexpr int B = 16;  // loads in flight per thread
+  for (int64_t f0 = t; f0 < total; f0 += (int64_t)B * THREADS) {
+    double v[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int64_t f = f0 + (int64_t)k * THREADS;
+      v[k] = f < total ? p[f] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) s += v[k];
+  }
   part[t] = s;
   __syncthreads();
   if (t < ncols) {
@@ -112,6 +122,17 @@ __global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, in
     for (int k = t; k < THREADS; k += stride) tot += part[k];
     out[t] = accumulate ? out[t] + scale * tot : scale * tot;
   }
+}
+
+// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD b % 8),
+// and each XCD has its own L2.  Renumbering so that XCD x gets one contiguous
+// run of logical blocks keeps spatially adjacent tiles -- and the neighbor
+// positions they gather -- inside one L2.  A bijection on [0, nblk).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int q = nblk / kXcds, r = nblk % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
 }
 
 // Packed upper-triangle index of the type pair (a, b).

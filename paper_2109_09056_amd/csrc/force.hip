@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   } else {
     load_table(a, tab);
   }
-  const int32_t i = blockIdx.x * kForceThreads + threadIdx.x;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + threadIdx.x;
   Acc s;
   const bool live = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
   } else {
     load_table(a, tab);
   }
-  const int32_t i = blockIdx.x * kForceThreads + threadIdx.x;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + threadIdx.x;
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
   double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
   if (i < a.n) {

@@ -19,6 +19,9 @@ namespace ljmd {
 namespace {
 
 constexpr int kSlots = 12;  // register slots: up to 768 candidates staged
+constexpr int kBatch = 16;  // home atoms whose rows are buffered in LDS at once
+constexpr int kRowCap = 128;              // longest row buffered in LDS
+constexpr int kRowStride = kRowCap + 1;   // odd stride: lanes reading row k hit distinct banks
 
 __global__ void k_fill_scalar(int32_t *p, int32_t val) { *p = val; }
 
@@ -96,7 +99,7 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
                                              int32_t h0, int32_t h1, int32_t total, int nslot,
                                              const int32_t *rs, const int32_t *pre, int32_t maxn,
                                              int32_t *__restrict__ nbr, int32_t *__restrict__ nnbr,
-                                             int32_t &maxc) {
+                                             int32_t *rowbuf, int32_t *rowcnt, int32_t &maxc) {
   const int lane = threadIdx.x & (kWave - 1);
   const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
   const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
@@ -115,33 +118,62 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
       qz[r] = x[3 * (int64_t)j + 2];
     }
   }
-  for (int32_t i = h0; i < h1; ++i) {
-    const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
-    int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
-    int32_t base = 0;
+  // Rows of up to kBatch home atoms are compacted into LDS first (when they fit)
+  // and then written out k by k: the atoms of a batch are consecutive, so each
+  // store instruction covers one contiguous run of a tile row instead of
+  // scattering 4-byte entries 256 bytes apart.
+  const bool buffered = maxn <= kRowCap;
+  for (int32_t b0 = h0; b0 < h1; b0 += kBatch) {
+    const int nb = h1 - b0 < kBatch ? h1 - b0 : kBatch;
+    for (int bi = 0; bi < nb; ++bi) {
+      const int32_t i = b0 + bi;
+      const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1],
+                   zi = x[3 * (int64_t)i + 2];
+      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      int32_t base = 0;
 #pragma unroll
-    for (int r = 0; r < kSlots; ++r) {
-      if (r < nslot) {
-        double dx = xi - qx[r], dy = yi - qy[r], dz = zi - qz[r];
-        if constexpr (WRAP) {
-          dx = min_image(dx, L0, iL0);
-          dy = min_image(dy, L1, iL1);
-          dz = min_image(dz, L2, iL2);
+      for (int r = 0; r < kSlots; ++r) {
+        if (r < nslot) {
+          double dx = xi - qx[r], dy = yi - qy[r], dz = zi - qz[r];
+          if constexpr (WRAP) {
+            dx = min_image(dx, L0, iL0);
+            dy = min_image(dy, L1, iL1);
+            dz = min_image(dz, L2, iL2);
+          }
+          const double r2 = dist2(dx, dy, dz);
+          const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
+          const uint64_t m = __ballot(ok);
+          if (ok) {
+            const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
+                                         (uint32_t)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (k < maxn) {
+              if (buffered)
+                rowbuf[bi * kRowStride + k] = qj[r];
+              else
+                row[(int64_t)k * kWave] = qj[r];
+            }
+          }
+          base += (int32_t)__popcll(m);
         }
-        const double r2 = dist2(dx, dy, dz);
-        const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
-        const uint64_t m = __ballot(ok);
-        if (ok) {
-          const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
-                                       (uint32_t)(m >> 32),
-                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (k < maxn) row[(int64_t)k * kWave] = qj[r];
-        }
-        base += (int32_t)__popcll(m);
       }
+      const int32_t kept = base < maxn ? base : maxn;
+      if (lane == 0) {
+        nnbr[i] = kept;
+        rowcnt[bi] = kept;
+      }
+      maxc = base > maxc ? base : maxc;
     }
-    if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
-    maxc = base > maxc ? base : maxc;
+    if (buffered) {
+      __syncthreads();  // rowbuf / rowcnt written by other lanes of this one-wavefront block
+      const int32_t mine = lane < nb ? rowcnt[lane] : 0;
+      const int32_t kmax = wave_max(mine);
+      const int32_t i = b0 + lane;
+      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      for (int32_t k = 0; k < kmax; ++k)
+        if (k < mine) row[(int64_t)k * kWave] = rowbuf[lane * kRowStride + k];
+      __syncthreads();  // before the next batch overwrites rowbuf
+    }
   }
 }
 
@@ -154,8 +186,10 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
                                                  int32_t *__restrict__ max_count) {
   __shared__ int32_t rs[27];
   __shared__ int32_t pre[28];
+  __shared__ int32_t rowbuf[kBatch * kRowStride];
+  __shared__ int32_t rowcnt[kBatch];
   const int lane = threadIdx.x;
-  const int32_t c = blockIdx.x;
+  const int32_t c = xcd_block(blockIdx.x, gridDim.x);
   const int32_t h0 = cell_start[c];
   const int32_t h1 = cell_start[c + 1];
   if (h0 == h1) return;
@@ -175,9 +209,11 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
   }
   if (nslot <= kSlots) {
     if (wrap)
-      build_staged<HALF, true>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, maxc);
+      build_staged<HALF, true>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, rowbuf,
+                               rowcnt, maxc);
     else
-      build_staged<HALF, false>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, maxc);
+      build_staged<HALF, false>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr,
+                                rowbuf, rowcnt, maxc);
   } else {
     const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
     const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
