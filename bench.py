@@ -1,10 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the short-range LJ MD hot path on one MI355X.
 
-A step is one velocity-Verlet MD step of the whole path: half kick + drift +
-wrap, the binned re-sort and Verlet-list rebuild every 20 steps, LJ forces
-with per-atom energy, energy and virial, and the second half kick with the
-kinetic energy.  Workload: the 500,000-atom dense LJ liquid (fcc 50^3 cells
+A step is one velocity-Verlet MD step of the whole path: the binned re-sort
+and Verlet-list rebuild every 20 steps, LJ forces with per-atom energy,
+energy and virial, the closing half kick with the kinetic energy and the
+next step's opening half kick, drift and wrap (one fused launch on the full
+list plus one reduction launch).  Workload: the 500,000-atom dense LJ liquid (fcc 50^3 cells
 at rho* = 0.8442, T* = 1.44, rc 2.5, skin 0.3, dt 0.005), synthetic and
 seeded, inputs resident in HBM before the timed region.
 
@@ -213,11 +214,13 @@ def main():
     value = n * args.steps / t_mixed
     nbar = float(sim.nl.nnbr.double().mean().item())
     force_ms = statistics.mean(fms)
-    force_bytes = n * (4.0 * nbar + 24 + 24 + 8 + 4)
+    # fused step kernel, per atom: list row 4*nbar + count 4 + x 24 + F 24 + e 8
+    # + v read/write 48 + next positions 24 (neighbor positions are cache hits)
+    force_bytes = n * (4.0 * nbar + 4 + 24 + 24 + 8 + 48 + 24)
     achieved = force_bytes / (force_ms * 1e-3) / 1e9
     th = sim.thermo()
     log(f"[bench] mixed: {t_mixed * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s, "
-        f"force call {force_ms * 1e3:.1f} us, mean list {nbar:.2f}, T {th['temp']:.4f}")
+        f"fused step launch {force_ms * 1e3:.1f} us, mean list {nbar:.2f}, T {th['temp']:.4f}")
     line = {
         "metric": "atom-steps/s LJ force+neighbor, mixed vs FP64, 500k atoms; bwd/fwd time ratio",
         "value": round(value, 1), "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -229,7 +232,9 @@ def main():
                                f"T 1.44, rc 2.5, skin 0.3, dt 0.005, rebuild every 20, full list",
                    "natoms": n, "precision": "mixed", "list": "full",
                    "mean_list_length": round(nbar, 3), "maxn": sim.nl.maxn},
-        "roofline": {"bound": "hbm", "kernel": "k_force_full<mixed> (+ energy/virial column sum)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_force_full<mixed, step> fused force+integration "
+                               "(+ energy/virial/KE column sum)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": FORCE_TRAFFIC,
                      "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
@@ -238,7 +243,7 @@ def main():
         t64, f64ms, sim64 = md_run(w, s, ops.FP64, args.steps, args.warmup, dev)
         line["fp64"] = {"value": round(n * args.steps / t64, 1), "unit": "atom-steps/s",
                         "ms_per_step": round(t64 * 1e3 / args.steps, 5),
-                        "force_call_us": round(statistics.mean(f64ms) * 1e3, 3),
+                        "step_launch_us": round(statistics.mean(f64ms) * 1e3, 3),
                         "mixed_over_fp64": round(t64 / t_mixed, 4)}
         log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
         line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),

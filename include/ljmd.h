@@ -215,6 +215,34 @@ int ljmd_force_backward(const ljmd_box *box, int precision, double rc, int32_t n
                         double *geps, double *gsigma, int accumulate, void *ws,
                         size_t ws_bytes, void *stream);
 
+/*
+ * ljmd_md_step -- one fused velocity-Verlet step on a FULL list: the forces of
+ * ljmd_compute_forces at x, then for every atom the closing half kick
+ * v += dt/2 F/m (the kinetic energy is taken here), and, when open_next is
+ * nonzero, the next step's opening half kick v += dt/2 F/m, drift
+ * x_next = x + dt v and wrap (paper: the MD timestep computes each particle's
+ * forces and propagates it -- Introduction; CabanaMD keeps force kernel and
+ * integration together in the application).  Positions, velocities and
+ * forces are bitwise the same as ljmd_compute_forces followed by
+ * ljmd_integrate(LJMD_KICK) and ljmd_integrate(LJMD_KICK_DRIFT); the kinetic
+ * energy is summed per atom first, so it can differ from LJMD_KICK's in the
+ * last bits.
+ *   x        positions at this step (read by every lane: must not alias x_next)
+ *   v        [n][3] in/out: half-step velocities in, updated velocities out
+ *   x_next   [n][3] output positions of the next step (ignored, may be NULL,
+ *            when open_next == 0)
+ *   F        [n][3] output forces, or NULL
+ *   e_atom   [n] output per-atom energy, or NULL
+ *   ev       [8] output: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, kinetic energy
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_FORCES, n, 0, ntypes)
+ * Other arguments as in ljmd_compute_forces and ljmd_integrate.
+ */
+int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                 const double *eps_packed, const double *sigma_packed, int64_t n,
+                 const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
+                 int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
+                 double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- elementwise steps of the discrete velocity-Verlet adjoint ----
  *
  * Reverse of one step (x_n, v_n) -> (x_{n+1}, v_{n+1}) once the VJP at

@@ -47,6 +47,8 @@ SIGNATURES = {
     "ljmd_integrate": (_int, [_int, _dbl, _dbl, _box, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "ljmd_force_backward": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32,
                                    _p, _p, _p, _p, _int, _p, _sz, _p]),
+    "ljmd_md_step": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32, _dbl,
+                            _dbl, _p, _p, _int, _p, _p, _p, _p, _sz, _p]),
     "ljmd_adjoint_kick": (_int, [_i64, _dbl, _dbl, _p, _p, _p, _p]),
     "ljmd_traj_loss": (_int, [_box, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "ljmd_scatter_rows": (_int, [_i64, _i32, _p, _p, _p, _p]),

@@ -21,6 +21,11 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
                   const double *eps, const double *sig, int64_t n, const double *x,
                   const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
                   double *F, double *e_atom, double *ev, void *ws, hipStream_t st);
+int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                   const double *sig, int64_t n, const double *x, const int32_t *type,
+                   const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double dt, double mass,
+                   double *v, double *x_next, int open_next, double *F, double *e_atom, double *ev,
+                   void *ws, hipStream_t st);
 size_t bwd_workspace(int64_t n, int32_t ntypes);
 int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
                     const double *sig, int64_t n, const double *x, const int32_t *type,
@@ -251,6 +256,33 @@ int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64
   if (ke) LJMD_TRY(check_ws(ws, ws_bytes, stream_workspace(n)));
   BoxK b = drift ? make_box(box) : BoxK{};
   return launch_integrate(stage, dt, mass, b, n, x, v, F, ke, ws, (hipStream_t)stream);
+}
+
+int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                 const double *eps_packed, const double *sigma_packed, int64_t n,
+                 const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
+                 int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
+                 double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (!isfinite(dt) || dt == 0.0) return set_error(LJMD_EINVAL, "dt = %g", dt);
+  if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g", mass);
+  if (open_next != 0 && open_next != 1)
+    return set_error(LJMD_EINVAL, "open_next = %d must be 0 or 1", open_next);
+  if (!ev) return set_error(LJMD_EINVAL, "ev is NULL");
+  if (n > 0 && (!x || !nbr || !nnbr || !v || (open_next && !x_next)))
+    return set_error(LJMD_EINVAL, "x/nbr/nnbr/v/x_next is NULL");
+  if (n > 0 && open_next && x_next == x)
+    return set_error(LJMD_EINVAL, "x_next must not alias x");
+  LJMD_TRY(check_ws(ws, ws_bytes, force_workspace(n)));
+  return launch_md_step(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x, type,
+                        nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, ev, ws,
+                        (hipStream_t)stream);
 }
 
 int ljmd_force_backward(const ljmd_box *box, int precision, double rc, int32_t ntypes,

@@ -20,8 +20,6 @@
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
 // column-sum launch (deterministic).
-#include <stdlib.h>
-
 #include "common.h"
 
 namespace ljmd {
@@ -46,6 +44,11 @@ struct ForceArgs {
   double *F;
   double *e_atom;
   double *partial;
+  // fused velocity-Verlet step (k_force_full<..., STEP = true> only)
+  double *v;
+  double *x_next;
+  double dt, hdt, mass;
+  int unit_mass, open_next;
 };
 
 namespace {
@@ -177,10 +180,15 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
   }
 }
 
-template <bool MIXED, bool T1, bool EV, int U, bool SKIP>
+// STEP: after the row, the lane also finishes its atom's velocity-Verlet step
+// -- closing half kick (kinetic energy taken there), and when open_next the
+// next step's half kick, drift and wrap into x_next -- with exactly the
+// operations of ljmd_integrate, so the trajectory is bitwise the same as the
+// unfused calls.  Partial rows then carry the kinetic energy in column 7.
+template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP>
 __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
-  __shared__ double red[kForceWaves * 7];
+  __shared__ double red[kForceWaves * 8];
   Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
@@ -189,6 +197,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   }
   const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + threadIdx.x;
   Acc s;
+  double ke = 0.0;
   const bool live = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0;
   if (live) {
@@ -211,15 +220,41 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
       walk_row<MIXED, T1, EV, U, false>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     else
       walk_row<MIXED, T1, EV, U, true>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
-    a.F[3 * (int64_t)i] = s.fx;
-    a.F[3 * (int64_t)i + 1] = s.fy;
-    a.F[3 * (int64_t)i + 2] = s.fz;
+    if (!STEP || a.F) {
+      a.F[3 * (int64_t)i] = s.fx;
+      a.F[3 * (int64_t)i + 1] = s.fy;
+      a.F[3 * (int64_t)i + 2] = s.fz;
+    }
     if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
+    if constexpr (STEP) {
+      const double f[3] = {s.fx, s.fy, s.fz};
+      const double xo[3] = {xi, yi, zi};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t q = 3 * (int64_t)i + k;
+        double kick = a.hdt * f[k];
+        if (!a.unit_mass) kick = kick / a.mass;
+        const double vn = a.v[q] + kick;
+        ke = __builtin_fma(vn, vn, ke);
+        if (a.open_next) {
+          const double L = a.b.L[k];
+          const double vh = vn + kick;
+          double xq = xo[k] + a.dt * vh;
+          if (xq >= L) xq -= L;
+          else if (xq < 0.0) xq += L;
+          if (xq >= L) xq -= L;
+          a.v[q] = vh;
+          a.x_next[q] = xq;
+        } else {
+          a.v[q] = vn;
+        }
+      }
+    }
   }
   if constexpr (EV) {
-    const double v[7] = {0.5 * s.e,   0.5 * s.wxx, 0.5 * s.wyy, 0.5 * s.wzz,
-                         0.5 * s.wxy, 0.5 * s.wxz, 0.5 * s.wyz};
-    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+    const double v[8] = {0.5 * s.e,   0.5 * s.wxx, 0.5 * s.wyy, 0.5 * s.wzz,
+                         0.5 * s.wxy, 0.5 * s.wxz, 0.5 * s.wyz, 0.5 * a.mass * ke};
+    block_sum<kForceWaves, 8>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
   }
 }
 
@@ -293,33 +328,16 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
   }
 }
 
-// Loop-shape knobs of the full-list kernel, for tuning runs: LJMD_FORCE_UNROLL
-// (1, 2, 4, 8) and LJMD_FORCE_INTERIOR (0/1).  Both shapes compute identical
-// results; the defaults are the measured best on MI355X.
-inline int knob(const char *name, int dflt) {
-  const char *v = getenv(name);
-  return v ? atoi(v) : dflt;
-}
+// Full-list loop shape: 8 slots per iteration with the exact interior fast
+// path (measured best on MI355X against 1, 2 and 4 slots, with and without it).
+constexpr int kUnroll = 8;
 
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
-  if (kind == LJMD_HALF) {
+  if (kind == LJMD_HALF)
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
-    return;
-  }
-  const int u = knob("LJMD_FORCE_UNROLL", 8);
-  const bool skip = knob("LJMD_FORCE_INTERIOR", 1) != 0;
-#define LJMD_FULL(U, S) k_force_full<MIXED, T1, EV, U, S><<<nblk, kForceThreads, 0, st>>>(a)
-  if (u >= 8) {
-    if (skip) LJMD_FULL(8, true); else LJMD_FULL(8, false);
-  } else if (u >= 4) {
-    if (skip) LJMD_FULL(4, true); else LJMD_FULL(4, false);
-  } else if (u == 2) {
-    if (skip) LJMD_FULL(2, true); else LJMD_FULL(2, false);
-  } else {
-    if (skip) LJMD_FULL(1, true); else LJMD_FULL(1, false);
-  }
-#undef LJMD_FULL
+  else
+    k_force_full<MIXED, T1, EV, kUnroll, true, false><<<nblk, kForceThreads, 0, st>>>(a);
 }
 
 template <bool MIXED>
@@ -344,7 +362,7 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
                   const double *eps, const double *sig, int64_t n, const double *x,
                   const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
                   double *F, double *e_atom, double *ev, void *ws, hipStream_t st) {
-  ForceArgs a;
+  ForceArgs a{};
   a.b = b;
   a.rc = rc;
   a.rc2 = rc * rc;
@@ -376,6 +394,53 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   }
   if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces");
+}
+
+int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                   const double *sig, int64_t n, const double *x, const int32_t *type,
+                   const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double dt, double mass,
+                   double *v, double *x_next, int open_next, double *F, double *e_atom, double *ev,
+                   void *ws, hipStream_t st) {
+  ForceArgs a{};
+  a.b = b;
+  a.rc = rc;
+  a.rc2 = rc * rc;
+  a.ntypes = ntypes;
+  a.eps = eps;
+  a.sig = sig;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.type = type;
+  a.nbr = nbr;
+  a.nnbr = nnbr;
+  a.maxn = maxn;
+  a.F = F;
+  a.e_atom = e_atom;
+  a.partial = (double *)ws;
+  a.v = v;
+  a.x_next = x_next;
+  a.dt = dt;
+  a.hdt = 0.5 * dt;
+  a.mass = mass;
+  a.unit_mass = mass == 1.0;
+  a.open_next = open_next;
+  const unsigned nblk = force_blocks(n);
+  const bool mixed = precision == LJMD_MIXED;
+  const bool t1 = ntypes == 1;
+#define LJMD_STEP(M, T) \
+  k_force_full<M, T, true, kUnroll, true, true><<<nblk, kForceThreads, 0, st>>>(a)
+  if (n > 0) {
+    if (mixed) {
+      if (t1) LJMD_STEP(true, true); else LJMD_STEP(true, false);
+    } else {
+      if (t1) LJMD_STEP(false, true); else LJMD_STEP(false, false);
+    }
+  } else {
+    k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
+  }
+#undef LJMD_STEP
+  k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 8, a.partial, ev, 1.0, 0);
+  return check_launch("ljmd_md_step");
 }
 
 }  // namespace ljmd

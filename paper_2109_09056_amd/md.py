@@ -13,8 +13,10 @@ Velocity Verlet with a fixed rebuild cadence (no displacement check):
     every `rebuild_every` steps: re-sort by cell and rebuild the list
     F = F(x)                                   (ljmd_compute_forces)
     v += dt/2 F/m                              (ljmd_integrate KICK)
-Inside one call the closing kick of a step and the opening kick + drift of
-the next run as one launch (ljmd_integrate KICK_KICK_DRIFT, bitwise equal).
+With a FULL list the force call and the kicks of a step run as one launch
+(ljmd_md_step, bitwise equal to the separate calls); with a HALF list the
+closing kick of a step and the opening kick + drift of the next run as one
+launch (ljmd_integrate KICK_KICK_DRIFT).
 """
 from __future__ import annotations
 
@@ -123,10 +125,13 @@ class LJSim:
         # ping-pong buffers for the re-sort
         self._alt = (torch.empty_like(x), torch.empty_like(v), torch.empty_like(types),
                      torch.empty(n, dtype=torch.int64, device=dev))
+        self.xn = torch.empty_like(x)  # next-step positions of the fused step
         self.F = torch.empty_like(x)
         self.e_atom = torch.empty(n, dtype=torch.float64, device=dev)
-        self.ev = torch.zeros(7, dtype=torch.float64, device=dev)
-        self.ke = torch.zeros(1, dtype=torch.float64, device=dev)
+        # E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, kinetic energy
+        self.ev = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.ke = self.ev[7:]
+        self._fargs = {}
         self.cell_start = None
         for op in (ops.OP_FORCES, ops.OP_INTEGRATE):
             self._ws[op] = torch.empty(max(ops.workspace_bytes(op, n), 8), dtype=torch.uint8,
@@ -145,13 +150,14 @@ class LJSim:
                      self.ids if self.ids is not None else torch.empty_like(io))
         self.x, self.v, self.types, self.ids = xo, vo, to, io
         self.nl.build(self.x, self.cell_start)
+        self._fargs = {}
 
     # ------------------------------------------------------------------- step
     def compute_forces(self, energy=True):
         ops.compute_forces(self.L, self.precision, self.kind, self.rc, self.eps, self.sigma,
                            self.x, self.types, self.nl.nbr, self.nl.nnbr, self.nl.maxn, F=self.F,
                            e_atom=self.e_atom if energy else None,
-                           ev=self.ev if energy else None, want_energy=energy,
+                           ev=self.ev[:7] if energy else None, want_energy=energy,
                            ws=self._ws[ops.OP_FORCES])
 
     def _step_args(self, energy):
@@ -172,16 +178,61 @@ class LJSim:
         kkd = (KICK_KICK_DRIFT,) + kk[1:]
         return kd, fc, kk, kkd
 
-    def step(self, nsteps=1, energy=True, force_timer=None):
-        """Advance nsteps velocity-Verlet steps; energy: E, W and KE every step.
+    def _fused_args(self, energy):
+        """ljmd_md_step argument tuples (opening the next step, closing the call) for the
+        current position buffer; cached per buffer until the next rebuild."""
+        key = (self.x.data_ptr(), energy)
+        if key not in self._fargs:
+            p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            wsf = self._ws[ops.OP_FORCES]
+            head = (ctypes.byref(self._box), self.precision, self.rc, self.ntypes, p(self.eps),
+                    p(self.sigma), self.n, p(self.x), p(self.types), p(self.nl.nbr),
+                    p(self.nl.nnbr), self.nl.maxn, self.dt, self.mass, p(self.v), p(self.xn))
+            tail = (p(self.F), p(self.e_atom) if energy else None, p(self.ev), p(wsf),
+                    wsf.numel(), st)
+            self._fargs[key] = (head + (1,) + tail, head + (0,) + tail)
+        return self._fargs[key]
 
-        force_timer: optional list receiving (start, end) timing events recorded on the
-        current stream around every force call.
+    def step(self, nsteps=1, energy=True, force_timer=None):
+        """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
+        (the per-atom energy only when energy is true).
+
+        FULL lists run one fused launch per step (ljmd_md_step); HALF lists run the
+        separate force and integration calls.  force_timer: optional list receiving
+        (start, end) timing events recorded on the current stream around every
+        force launch.
         """
-        lib = _lib.load()
-        integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
         if nsteps <= 0:
             return self
+        lib = _lib.load()
+        if self.kind != FULL:
+            return self._step_unfused(nsteps, energy, force_timer)
+        integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
+        kd = self._step_args(energy)[0]
+        _lib.check(integrate(*kd), "ljmd_integrate")
+        for s in range(nsteps):
+            self.step_count += 1
+            if self.step_count % self.rebuild_every == 0:
+                self.rebuild()
+            last = s == nsteps - 1
+            args = self._fused_args(energy)[1 if last else 0]
+            if force_timer is not None:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                _lib.check(mdstep(*args), "ljmd_md_step")
+                b.record()
+                force_timer.append((a, b))
+            else:
+                _lib.check(mdstep(*args), "ljmd_md_step")
+            if not last:
+                self.x, self.xn = self.xn, self.x
+        return self
+
+    def _step_unfused(self, nsteps, energy, force_timer):
+        lib = _lib.load()
+        integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
         kd, fc, kk, kkd = self._step_args(energy)
         _lib.check(integrate(*kd), "ljmd_integrate")
         for s in range(nsteps):
@@ -206,13 +257,13 @@ class LJSim:
     # ---------------------------------------------------------------- reports
     def thermo(self):
         ev = self.ev.cpu()
-        ke = float(self.ke.cpu()[0])
+        ke = float(ev[7])
         pe = float(ev[0])
         vol = self.L[0] * self.L[1] * self.L[2]
         temp = 2.0 * ke / (3 * self.n - 3)
         press = (self.n * temp + float(ev[1] + ev[2] + ev[3]) / 3.0) / vol
         return dict(step=self.step_count, pe=pe, ke=ke, etot=pe + ke, temp=temp, press=press,
-                    virial=ev[1:].tolist(), builds=self.nl.builds, maxn=self.nl.maxn)
+                    virial=ev[1:7].tolist(), builds=self.nl.builds, maxn=self.nl.maxn)
 
     def in_caller_order(self, t):
         """Rows of a sorted-order tensor rearranged into the caller's atom order (ids)."""

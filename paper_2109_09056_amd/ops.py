@@ -150,6 +150,39 @@ def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn
     return F, e_atom, ev
 
 
+def md_step(L, precision, rc, eps, sigma, x, types, nbr, nnbr, maxn, dt, mass, v, x_next=None,
+            open_next=True, F=None, e_atom=None, ev=None, ws=None):
+    """Fused velocity-Verlet step on a FULL list; returns (x_next, F, ev[8])."""
+    n = x.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (n, 3))
+    _need(v, "v", torch.float64, (n, 3), dev)
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if open_next and x_next is None:
+        x_next = torch.empty_like(x)
+    if ev is None:
+        ev = torch.empty(8, dtype=torch.float64, device=dev)
+    _need(x_next, "x_next", torch.float64, (n, 3), dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_atom, "e_atom", torch.float64, (n,), dev)
+    _need(ev, "ev", torch.float64, (8,), dev)
+    ws, need = _ws(OP_FORCES, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_md_step(
+        ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, _ptr(x),
+        _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), float(dt), float(mass), _ptr(v),
+        _ptr(x_next), 1 if open_next else 0, _ptr(F), _ptr(e_atom), _ptr(ev), _ptr(ws), need,
+        _stream(dev)), "ljmd_md_step")
+    return x_next, F, ev
+
+
 def integrate(stage, dt, mass, L, x, v, F, ke=None, ws=None):
     """In-place velocity-Verlet stage; ke (device scalar) receives 1/2 m sum v^2 if given."""
     n = v.shape[0]

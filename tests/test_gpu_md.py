@@ -43,6 +43,45 @@ def test_integrate_stages_bitwise(dev, orc):
         assert float(ke.item()) == pytest.approx(0.5 * mass * (vo * vo).sum(), rel=1e-13)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("ntypes", [1, 2])
+def test_md_step_matches_separate_calls(dev, prec, ntypes):
+    """ljmd_md_step == compute_forces + integrate(KICK) + integrate(KICK_DRIFT), bitwise."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.Workload("t", 3, cells=8, ntypes=ntypes)
+    s = li.make_system(w)
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    sim = md.LJSim(w.box, eps=s["eps"], sigma=s["sigma"], precision=P, device=dev)
+    sim.load(s["x"], s["v"], s["types"])
+    sim.step(3)
+    x0, v0 = sim.x.clone(), sim.v.clone()
+    for mass in (1.0, 1.7):
+        # fused
+        v1 = v0.clone()
+        xn, F1, ev1 = ops.md_step(w.box, P, w.rc, sim.eps, sim.sigma, x0, sim.types, sim.nl.nbr,
+                                  sim.nl.nnbr, sim.nl.maxn, w.dt, mass, v1, F=torch.empty_like(x0))
+        # separate calls
+        x2, v2 = x0.clone(), v0.clone()
+        F2, _, ev2 = ops.compute_forces(w.box, P, ops.FULL, w.rc, sim.eps, sim.sigma, x2,
+                                        sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+        ke = torch.zeros(1, dtype=torch.float64, device=dev)
+        ops.integrate(ops.KICK, w.dt, mass, w.box, x2, v2, F2, ke=ke)
+        ops.integrate(ops.KICK_DRIFT, w.dt, mass, w.box, x2, v2, F2)
+        assert torch.equal(F1, F2)
+        assert torch.equal(v1, v2)
+        assert torch.equal(xn, x2)
+        assert torch.equal(ev1[:7], ev2)
+        assert float(ev1[7]) == pytest.approx(float(ke), rel=1e-13)
+        # closing a call: velocities kicked once, no drift
+        v3 = v0.clone()
+        ops.md_step(w.box, P, w.rc, sim.eps, sim.sigma, x0, sim.types, sim.nl.nbr, sim.nl.nnbr,
+                    sim.nl.maxn, w.dt, mass, v3, open_next=False)
+        v4 = v0.clone()
+        ops.integrate(ops.KICK, w.dt, mass, w.box, x0.clone(), v4, F2)
+        assert torch.equal(v3, v4)
+
+
 def test_nve_lj256_matches_oracle_trajectory(dev, orc):
     """100 FP64 steps with rebuilds every 20: GPU and oracle Verlet-mirror trajectories agree."""
     from paper_2109_09056_amd import md, ops
