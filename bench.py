@@ -71,13 +71,14 @@ def md_run(w, s, precision, steps, warmup, dev):
                    rebuild_every=w.rebuild_every, device=dev)
     sim.load(s["x"], s["v"])
     sim.step(warmup)
-    timer = []
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps, force_timer=timer)
+    sim.step(steps, force_events=iter(events))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    force_ms = [a.elapsed_time(b) for a, b in timer]
+    force_ms = [a.elapsed_time(b) for a, b in events]
     return t1 - t0, force_ms, sim
 
 

@@ -181,10 +181,11 @@ class LJSim:
     def _fused_args(self, energy):
         """ljmd_md_step argument tuples (opening the next step, closing the call) for the
         current position buffer; cached per buffer until the next rebuild."""
-        key = (self.x.data_ptr(), energy)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        key = (self.x.data_ptr(), energy, stream)
         if key not in self._fargs:
             p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
-            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            st = ctypes.c_void_p(stream)
             wsf = self._ws[ops.OP_FORCES]
             head = (ctypes.byref(self._box), self.precision, self.rc, self.ntypes, p(self.eps),
                     p(self.sigma), self.n, p(self.x), p(self.types), p(self.nl.nbr),
@@ -194,20 +195,20 @@ class LJSim:
             self._fargs[key] = (head + (1,) + tail, head + (0,) + tail)
         return self._fargs[key]
 
-    def step(self, nsteps=1, energy=True, force_timer=None):
+    def step(self, nsteps=1, energy=True, force_events=None):
         """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
         (the per-atom energy only when energy is true).
 
         FULL lists run one fused launch per step (ljmd_md_step); HALF lists run the
-        separate force and integration calls.  force_timer: optional list receiving
-        (start, end) timing events recorded on the current stream around every
-        force launch.
+        separate force and integration calls.  force_events: optional iterator of
+        pre-created (start, end) timing events, recorded on the current stream
+        around every force launch.
         """
         if nsteps <= 0:
             return self
         lib = _lib.load()
         if self.kind != FULL:
-            return self._step_unfused(nsteps, energy, force_timer)
+            return self._step_unfused(nsteps, energy, force_events)
         integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
         kd = self._step_args(energy)[0]
         _lib.check(integrate(*kd), "ljmd_integrate")
@@ -217,20 +218,18 @@ class LJSim:
                 self.rebuild()
             last = s == nsteps - 1
             args = self._fused_args(energy)[1 if last else 0]
-            if force_timer is not None:
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
+            if force_events is not None:
+                a, b = next(force_events)
                 a.record()
                 _lib.check(mdstep(*args), "ljmd_md_step")
                 b.record()
-                force_timer.append((a, b))
             else:
                 _lib.check(mdstep(*args), "ljmd_md_step")
             if not last:
                 self.x, self.xn = self.xn, self.x
         return self
 
-    def _step_unfused(self, nsteps, energy, force_timer):
+    def _step_unfused(self, nsteps, energy, force_events):
         lib = _lib.load()
         integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
         kd, fc, kk, kkd = self._step_args(energy)
@@ -240,13 +239,11 @@ class LJSim:
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
                 kd, fc, kk, kkd = self._step_args(energy)
-            if force_timer is not None:
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
+            if force_events is not None:
+                a, b = next(force_events)
                 a.record()
                 _lib.check(forces(*fc), "ljmd_compute_forces")
                 b.record()
-                force_timer.append((a, b))
             else:
                 _lib.check(forces(*fc), "ljmd_compute_forces")
             # closing half kick of this step fused with the opening kick + drift of the
