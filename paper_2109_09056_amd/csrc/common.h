@@ -54,6 +54,14 @@ __device__ __forceinline__ float recip32(float a) {
   return __builtin_fmaf(y, e, y);
 }
 
+// Value of v in lane `src` (wavefront-uniform src), through two scalar readlanes.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

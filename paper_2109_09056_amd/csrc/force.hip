@@ -284,8 +284,13 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
     const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
     const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
     const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
+    // Neighboring lanes hold similar rows; starting each lane at a different
+    // slot spreads the simultaneous atomic updates over different atoms.
+    const int32_t rot = cnt > 0 ? (int32_t)((5u * (threadIdx.x & (kWave - 1))) % (uint32_t)cnt) : 0;
     for (int32_t k = 0; k < cnt; ++k) {
-      const int32_t j = row[(int64_t)k * kWave];
+      int32_t kk = k + rot;
+      if (kk >= cnt) kk -= cnt;
+      const int32_t j = row[(int64_t)kk * kWave];
       const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
       const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
       const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);

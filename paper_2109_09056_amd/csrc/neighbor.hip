@@ -123,12 +123,24 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   // store instruction covers one contiguous run of a tile row instead of
   // scattering 4-byte entries 256 bytes apart.
   const bool buffered = maxn <= kRowCap;
+  // home positions: lane l holds atom c0 + l of the current chunk of 64, read
+  // back by every lane with a scalar readlane (no load latency per home atom)
+  double hx = 0.0, hy = 0.0, hz = 0.0;
   for (int32_t b0 = h0; b0 < h1; b0 += kBatch) {
     const int nb = h1 - b0 < kBatch ? h1 - b0 : kBatch;
+    if ((b0 - h0) % kWave == 0) {
+      const int32_t ih = b0 + lane;
+      if (ih < h1) {
+        hx = x[3 * (int64_t)ih];
+        hy = x[3 * (int64_t)ih + 1];
+        hz = x[3 * (int64_t)ih + 2];
+      }
+    }
     for (int bi = 0; bi < nb; ++bi) {
       const int32_t i = b0 + bi;
-      const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1],
-                   zi = x[3 * (int64_t)i + 2];
+      const int src = (b0 - h0) % kWave + bi;
+      const double xi = readlane_f64(hx, src), yi = readlane_f64(hy, src),
+                   zi = readlane_f64(hz, src);
       int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
       int32_t base = 0;
 #pragma unroll
