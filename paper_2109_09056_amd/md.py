@@ -132,6 +132,7 @@ class LJSim:
         self.ev = torch.zeros(8, dtype=torch.float64, device=dev)
         self.ke = self.ev[7:]
         self._fargs = {}
+        self._graphs = {}
         self.cell_start = None
         for op in (ops.OP_FORCES, ops.OP_INTEGRATE):
             self._ws[op] = torch.empty(max(ops.workspace_bytes(op, n), 8), dtype=torch.uint8,
@@ -195,14 +196,35 @@ class LJSim:
             self._fargs[key] = (head + (1,) + tail, head + (0,) + tail)
         return self._fargs[key]
 
-    def step(self, nsteps=1, energy=True, force_events=None):
+    def _window_graph(self, m, energy):
+        """HIP graph of m fused steps that each open the next one, from the current
+        buffers; captured once per buffer arrangement and replayed afterwards."""
+        key = (m, energy, self.x.data_ptr(), self.xn.data_ptr(), self.v.data_ptr(),
+               self.types.data_ptr(), self.nl.nbr.data_ptr(), self.nl.nnbr.data_ptr(),
+               self.nl.maxn)
+        g = self._graphs.get(key)
+        if g is None:
+            mdstep = _lib.load().ljmd_md_step
+            x0, xn0 = self.x, self.xn
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(m):
+                    _lib.check(mdstep(*self._fused_args(energy)[0]), "ljmd_md_step")
+                    self.x, self.xn = self.xn, self.x
+            self.x, self.xn = x0, xn0
+            self._graphs[key] = g
+        return g
+
+    def step(self, nsteps=1, energy=True, force_events=None, graphs=False):
         """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
         (the per-atom energy only when energy is true).
 
         FULL lists run one fused launch per step (ljmd_md_step); HALF lists run the
         separate force and integration calls.  force_events: optional iterator of
         pre-created (start, end) timing events, recorded on the current stream
-        around every force launch.
+        around every force launch.  graphs: replay the steps between two rebuilds
+        as one captured HIP graph (FULL lists, no timing events; bitwise the same
+        trajectory as launching them one by one).
         """
         if nsteps <= 0:
             return self
@@ -210,12 +232,24 @@ class LJSim:
         if self.kind != FULL:
             return self._step_unfused(nsteps, energy, force_events)
         integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
+        use_graphs = graphs and force_events is None
         kd = self._step_args(energy)[0]
         _lib.check(integrate(*kd), "ljmd_integrate")
-        for s in range(nsteps):
+        s = 0
+        while s < nsteps:
             self.step_count += 1
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
+            # steps from this one up to (not including) the next rebuild, all of which
+            # open a following step: one graph replay
+            m = min(self.rebuild_every - self.step_count % self.rebuild_every, nsteps - s - 1)
+            if use_graphs and m >= 2:
+                self._window_graph(m, energy).replay()
+                if m % 2:
+                    self.x, self.xn = self.xn, self.x
+                self.step_count += m - 1
+                s += m
+                continue
             last = s == nsteps - 1
             args = self._fused_args(energy)[1 if last else 0]
             if force_events is not None:
@@ -227,6 +261,7 @@ class LJSim:
                 _lib.check(mdstep(*args), "ljmd_md_step")
             if not last:
                 self.x, self.xn = self.xn, self.x
+            s += 1
         return self
 
     def _step_unfused(self, nsteps, energy, force_events):

@@ -188,3 +188,28 @@ def test_lj32k_trajectory_vs_oracle(dev, oracle_32k_run, prec, kind):
     assert th["builds"] == 51 and np.isfinite(th["etot"])
     assert abs(th["etot"] - e100) / w.natoms < 5e-3
     assert sim.v.sum(dim=0).abs().max().item() < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(dev, prec):
+    """Steps replayed from captured HIP graphs give bitwise the eager trajectory,
+    across rebuilds (eager work between replays) and repeated replays."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    runs = []
+    for graphs in (False, True):
+        sim = md.LJSim(w.box, precision=P, device=dev)
+        sim.load(s["x"], s["v"])
+        out = []
+        for chunk in (7, 45, 1, 60):
+            sim.step(chunk, graphs=graphs)
+            out.append((sim.x.clone(), sim.v.clone(), sim.F.clone(), sim.ev.clone()))
+        runs.append(out)
+        if graphs:
+            assert len(sim._graphs) >= 1
+    for (xa, va, fa, ea), (xb, vb, fb, eb) in zip(*runs):
+        assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(fa, fb)
+        assert torch.equal(ea, eb)
