@@ -215,7 +215,7 @@ class LJSim:
             self._graphs[key] = g
         return g
 
-    def step(self, nsteps=1, energy=True, force_events=None, graphs=False):
+    def step(self, nsteps=1, energy=True, force_events=None, graphs=False, on_positions=None):
         """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
         (the per-atom energy only when energy is true).
 
@@ -224,15 +224,17 @@ class LJSim:
         pre-created (start, end) timing events, recorded on the current stream
         around every force launch.  graphs: replay the steps between two rebuilds
         as one captured HIP graph (FULL lists, no timing events; bitwise the same
-        trajectory as launching them one by one).
+        trajectory as launching them one by one).  on_positions: optional callable
+        given, for every step in order, the positions tensor the force call of that
+        step reads (valid until the next launch on the stream; clone to keep it).
         """
         if nsteps <= 0:
             return self
         lib = _lib.load()
         if self.kind != FULL:
-            return self._step_unfused(nsteps, energy, force_events)
+            return self._step_unfused(nsteps, energy, force_events, on_positions)
         integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
-        use_graphs = graphs and force_events is None
+        use_graphs = graphs and force_events is None and on_positions is None
         kd = self._step_args(energy)[0]
         _lib.check(integrate(*kd), "ljmd_integrate")
         s = 0
@@ -259,12 +261,14 @@ class LJSim:
                 b.record()
             else:
                 _lib.check(mdstep(*args), "ljmd_md_step")
+            if on_positions is not None:
+                on_positions(self.x)
             if not last:
                 self.x, self.xn = self.xn, self.x
             s += 1
         return self
 
-    def _step_unfused(self, nsteps, energy, force_events):
+    def _step_unfused(self, nsteps, energy, force_events, on_positions=None):
         lib = _lib.load()
         integrate, forces = lib.ljmd_integrate, lib.ljmd_compute_forces
         kd, fc, kk, kkd = self._step_args(energy)
@@ -281,6 +285,8 @@ class LJSim:
                 b.record()
             else:
                 _lib.check(forces(*fc), "ljmd_compute_forces")
+            if on_positions is not None:
+                on_positions(self.x)
             # closing half kick of this step fused with the opening kick + drift of the
             # next one (same operations, one pass); the call ends on a plain half kick
             _lib.check(integrate(*(kk if s == nsteps - 1 else kkd)), "ljmd_integrate")

@@ -16,9 +16,11 @@ packed (eps, sigma) come back in the caller's atom order.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
-from . import ops
+from . import _lib, ops
 from ._lib import FP64, FULL
 from .md import LJSim
 
@@ -52,10 +54,9 @@ def backprop_trajectory(L, x0, v0, types, eps, sigma, xref, steps=20, checkpoint
     xref_s = ops.gather_rows(ids, torch.as_tensor(xref, dtype=torch.float64,
                                                   device=sim.device).contiguous())
     ckpt = {}
-    for k in range(steps):
-        if k % checkpoint_every == 0:
-            ckpt[k] = (sim.x.clone(), sim.v.clone(), sim.F.clone())
-        sim.step(1, energy=False)
+    for k in range(0, steps, checkpoint_every):
+        ckpt[k] = (sim.x.clone(), sim.v.clone(), sim.F.clone())
+        sim.step(min(checkpoint_every, steps - k), energy=False)
     xT = sim.x.clone()
     loss, xbar = ops.traj_loss(sim.L, sim.x, xref_s)
     vbar = torch.zeros_like(xbar)
@@ -64,28 +65,32 @@ def backprop_trajectory(L, x0, v0, types, eps, sigma, xref, steps=20, checkpoint
     gsig = torch.zeros_like(sim.eps)
     ws = torch.empty(ops.workspace_bytes(ops.OP_BACKWARD, sim.n, 0, ops._ntypes(sim.eps)),
                      dtype=torch.uint8, device=sim.device)
+    lib = _lib.load()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    box = _lib.make_box(sim.L)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(sim.device).cuda_stream)
     recompute_ok = True
-    starts = sorted(ckpt)
-    for s in reversed(starts):
+    for s in reversed(sorted(ckpt)):
         e = min(s + checkpoint_every, steps)
         x, v, F = ckpt[s]
         sim.x.copy_(x)
         sim.v.copy_(v)
         sim.F.copy_(F)
         sim.step_count = s  # keeps the recomputation clear of the rebuild cadence
-        xs = [sim.x.clone()]
-        for _ in range(s, e - 1):
-            sim.step(1, energy=False)
-            xs.append(sim.x.clone())
+        xs = [x]
+        # the force calls of steps s+1 .. e read x_{s+1} .. x_e
+        nrec = e - s if verify_recompute else e - s - 1
+        sim.step(nrec, energy=False, on_positions=lambda t: xs.append(t.clone()))
         if verify_recompute:
-            sim.step(1, energy=False)
             ref = ckpt[e][0] if e in ckpt else xT
-            recompute_ok &= bool(torch.equal(sim.x, ref))
+            recompute_ok &= bool(torch.equal(xs.pop(), ref))
         for n in range(e - 1, s - 1, -1):
-            ops.adjoint_kick(dt, 1.0 if n > 0 else 0.5, xbar, vbar, g)
-            ops.force_backward(sim.L, precision, rc, sim.eps, sim.sigma, xs[n - s], sim.types,
-                               nl.nbr, nl.nnbr, nl.maxn, g, gx=xbar, geps=geps, gsigma=gsig,
-                               accumulate=True, ws=ws)
+            _lib.check(lib.ljmd_adjoint_kick(sim.n, dt, 1.0 if n > 0 else 0.5, p(xbar), p(vbar),
+                                             p(g), stream), "ljmd_adjoint_kick")
+            _lib.check(lib.ljmd_force_backward(
+                ctypes.byref(box), precision, rc, sim.ntypes, p(sim.eps), p(sim.sigma), sim.n,
+                p(xs[n - s]), p(sim.types), p(nl.nbr), p(nl.nnbr), nl.maxn, p(g), p(xbar),
+                p(geps), p(gsig), 1, p(ws), ws.numel(), stream), "ljmd_force_backward")
     return TrajectoryResult(
         loss=loss, gx0=sim.in_caller_order(xbar), gv0=sim.in_caller_order(vbar), geps=geps,
         gsigma=gsig, xT=ops.scatter_rows(ids, xT), recompute_bitwise=recompute_ok, sim=sim)
