@@ -130,8 +130,8 @@ def bwd_fwd_forcematching(dev, reps=100):
 
 def bwd_fwd_trajectory(dev):
     """Backprop through 20 steps of the 256,000-atom two-type system (mixed), checkpoints
-    every 5: trajectory-level t(forward + checkpointed reverse) / t(forward) and the
-    kernel-level ratio on the same list."""
+    every 5: trajectory-level t(reverse pass, recomputation included) / t(forward pass
+    with checkpoint stores), best of 3, and the kernel-level ratio on the same list."""
     import torch
     import lj_inputs as li
     from paper_2109_09056_amd import ops, trajectory
@@ -143,17 +143,16 @@ def bwd_fwd_trajectory(dev):
                                      device=dev)
     sim = trajectory._forward_sim(w.box, x0, v0, ty, eps, sig, w.rc, w.skin, w.dt, 1.0,
                                   ops.MIXED, w.steps, dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(w.steps, energy=False)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref.cpu().numpy(),
-                                       steps=w.steps, checkpoint_every=w.checkpoint_every,
-                                       precision=ops.MIXED, device=dev, verify_recompute=False)
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t0
+    sim.step(w.steps, energy=False)  # warm-up of the forward kernels
+    best = None
+    for _ in range(3):
+        tm = {}
+        r = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref.cpu().numpy(),
+                                           steps=w.steps, checkpoint_every=w.checkpoint_every,
+                                           precision=ops.MIXED, device=dev,
+                                           verify_recompute=False, timings=tm)
+        if best is None or tm["forward_s"] + tm["reverse_s"] < best["forward_s"] + best["reverse_s"]:
+            best = tm
     s2 = r.sim
     nl = s2.nl
     g = torch.randn_like(s2.x)
@@ -163,8 +162,8 @@ def bwd_fwd_trajectory(dev):
     tb = event_time(lambda: ops.force_backward(w.box, ops.MIXED, w.rc, s2.eps, s2.sigma, s2.x,
                                                s2.types, nl.nbr, nl.nnbr, nl.maxn, g), 20)
     return {"steps": w.steps, "checkpoint_every": w.checkpoint_every,
-            "forward_s": round(t_fwd, 5), "forward_plus_reverse_s": round(t_all, 5),
-            "trajectory_ratio": round(t_all / t_fwd, 3),
+            "forward_s": round(best["forward_s"], 5), "reverse_s": round(best["reverse_s"], 5),
+            "trajectory_ratio": round(best["reverse_s"] / best["forward_s"], 3),
             "kernel_fwd_ms": round(tf, 5), "kernel_bwd_ms": round(tb, 5),
             "kernel_ratio": round(tb / tf, 3)}
 

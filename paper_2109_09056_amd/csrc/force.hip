@@ -118,65 +118,104 @@ struct Acc {
   double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
 };
 
-// Walk atom i's row, U slots per iteration: the U index loads, then the U
+// Address of atom j's position.  Narrow form (every index below 2^24): a
+// 32-bit byte offset from the array base, formed with the full-rate 24-bit
+// multiply; wide form: 64-bit index arithmetic.
+template <bool WIDE>
+__device__ __forceinline__ const double *pos_of(const double *x, int32_t j) {
+  if constexpr (WIDE)
+    return x + 3 * (int64_t)j;
+  else
+    return (const double *)((const char *)x + __umul24((uint32_t)j, 24u));
+}
+
+// One neighbor j of atom i: minimum image (WRAP), cutoff test, pair force and
+// the row's accumulators.  `valid` is false for padding slots of a short group.
+template <bool MIXED, bool T1, bool EV, bool WRAP>
+__device__ __forceinline__ void add_pair(const ForceArgs &a, double xi, double yi, double zi,
+                                         double xj, double yj, double zj, int32_t j, bool valid,
+                                         int ti, const Coef &c1, const double *tab, Acc &s) {
+  double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  if constexpr (WRAP) {
+    dx = min_image(dx, a.b.L[0], a.b.invL[0]);
+    dy = min_image(dy, a.b.L[1], a.b.invL[1]);
+    dz = min_image(dz, a.b.L[2], a.b.invL[2]);
+  }
+  const double r2 = dist2(dx, dy, dz);
+  if (valid && r2 < a.rc2) {
+    Coef c;
+    if constexpr (T1) {
+      c = c1;
+    } else {
+      const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
+      c = Coef{t[0], t[1], t[2], t[3]};
+    }
+    const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
+    s.fx += p.fx;
+    s.fy += p.fy;
+    s.fz += p.fz;
+    if constexpr (EV) {
+      s.e += p.u;
+      s.wxx = __builtin_fma(dx, p.fx, s.wxx);
+      s.wyy = __builtin_fma(dy, p.fy, s.wyy);
+      s.wzz = __builtin_fma(dz, p.fz, s.wzz);
+      s.wxy = __builtin_fma(dx, p.fy, s.wxy);
+      s.wxz = __builtin_fma(dx, p.fz, s.wxz);
+      s.wyz = __builtin_fma(dy, p.fz, s.wyz);
+    }
+  }
+}
+
+// Walk atom i's row in groups of U slots: the U index loads, then the U
 // position gathers, then the U pair evaluations, so several loads are in
-// flight per lane.  WRAP = false skips the minimum image; the caller only
-// takes that path when every atom of the wavefront is at least rc from all
-// box faces, where any pair closer than rc has the same raw and
-// minimum-image displacement, and any other pair has some |raw component|
-// above L/2 > rc and is rejected by the cutoff test either way.
-template <bool MIXED, bool T1, bool EV, int U, bool WRAP>
+// flight per lane.  Whole groups read their indices at fixed offsets from one
+// row pointer (no per-slot address arithmetic); the last, partial group loads
+// only slots below cnt and repeats the group's first index in the others.
+// Slots are visited in row order, so the sums are the same as one slot at a
+// time.  WRAP = false skips the minimum image; the caller only takes that
+// path when every atom of the wavefront is at least rc from all box faces,
+// where any pair closer than rc has the same raw and minimum-image
+// displacement, and any other pair has some |raw component| above L/2 > rc
+// and is rejected by the cutoff test either way.
+template <bool MIXED, bool T1, bool EV, int U, bool WRAP, bool WIDE>
 __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row, int32_t cnt,
                                          double xi, double yi, double zi, int ti,
                                          const Coef &c1, const double *tab, Acc &s) {
-  const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
-  const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
-  for (int32_t k = 0; k < cnt; k += U) {
+  const int32_t whole = cnt - cnt % U;
+  int32_t k = 0;
+  for (; k < whole; k += U, row += U * kWave) {
     int32_t j[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t kk = (u == 0 || k + u < cnt) ? k + u : k;
-      j[u] = row[(int64_t)kk * kWave];
-    }
+    for (int u = 0; u < U; ++u) j[u] = row[u * kWave];
     double xj[U], yj[U], zj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      xj[u] = a.x[3 * (int64_t)j[u]];
-      yj[u] = a.x[3 * (int64_t)j[u] + 1];
-      zj[u] = a.x[3 * (int64_t)j[u] + 2];
+      const double *p = pos_of<WIDE>(a.x, j[u]);
+      xj[u] = p[0];
+      yj[u] = p[1];
+      zj[u] = p[2];
     }
 #pragma unroll
+    for (int u = 0; u < U; ++u)
+      add_pair<MIXED, T1, EV, WRAP>(a, xi, yi, zi, xj[u], yj[u], zj[u], j[u], true, ti, c1, tab,
+                                    s);
+  }
+  if (k < cnt) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = row[(k + u < cnt ? u : 0) * kWave];
+    double xj[U], yj[U], zj[U];
+#pragma unroll
     for (int u = 0; u < U; ++u) {
-      double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
-      if constexpr (WRAP) {
-        dx = min_image(dx, L0, iL0);
-        dy = min_image(dy, L1, iL1);
-        dz = min_image(dz, L2, iL2);
-      }
-      const double r2 = dist2(dx, dy, dz);
-      if ((u == 0 || k + u < cnt) && r2 < a.rc2) {
-        Coef c;
-        if constexpr (T1) {
-          c = c1;
-        } else {
-          const double *t = tab + 4 * (ti * a.ntypes + a.type[j[u]]);
-          c = Coef{t[0], t[1], t[2], t[3]};
-        }
-        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
-        s.fx += p.fx;
-        s.fy += p.fy;
-        s.fz += p.fz;
-        if constexpr (EV) {
-          s.e += p.u;
-          s.wxx = __builtin_fma(dx, p.fx, s.wxx);
-          s.wyy = __builtin_fma(dy, p.fy, s.wyy);
-          s.wzz = __builtin_fma(dz, p.fz, s.wzz);
-          s.wxy = __builtin_fma(dx, p.fy, s.wxy);
-          s.wxz = __builtin_fma(dx, p.fz, s.wxz);
-          s.wyz = __builtin_fma(dy, p.fz, s.wyz);
-        }
-      }
+      const double *p = pos_of<WIDE>(a.x, j[u]);
+      xj[u] = p[0];
+      yj[u] = p[1];
+      zj[u] = p[2];
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      add_pair<MIXED, T1, EV, WRAP>(a, xi, yi, zi, xj[u], yj[u], zj[u], j[u], k + u < cnt, ti, c1,
+                                    tab, s);
   }
 }
 
@@ -185,7 +224,7 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
 // next step's half kick, drift and wrap into x_next -- with exactly the
 // operations of ljmd_integrate, so the trajectory is bitwise the same as the
 // unfused calls.  Partial rows then carry the kinetic energy in column 7.
-template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP>
+template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE>
 __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
   __shared__ double red[kForceWaves * 8];
@@ -217,9 +256,9 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
     const int32_t cnt = a.nnbr[i];
     const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
     if (SKIP && interior)
-      walk_row<MIXED, T1, EV, U, false>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+      walk_row<MIXED, T1, EV, U, false, WIDE>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     else
-      walk_row<MIXED, T1, EV, U, true>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+      walk_row<MIXED, T1, EV, U, true, WIDE>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     if (!STEP || a.F) {
       a.F[3 * (int64_t)i] = s.fx;
       a.F[3 * (int64_t)i + 1] = s.fy;
@@ -337,12 +376,17 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
 // path (measured best on MI355X against 1, 2 and 4 slots, with and without it).
 constexpr int kUnroll = 8;
 
+// Indices below 2^24 take the narrow (32-bit offset) gather addressing.
+constexpr int64_t kNarrowAtoms = int64_t(1) << 24;
+
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
   if (kind == LJMD_HALF)
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
+  else if (a.n <= kNarrowAtoms)
+    k_force_full<MIXED, T1, EV, kUnroll, true, false, false><<<nblk, kForceThreads, 0, st>>>(a);
   else
-    k_force_full<MIXED, T1, EV, kUnroll, true, false><<<nblk, kForceThreads, 0, st>>>(a);
+    k_force_full<MIXED, T1, EV, kUnroll, true, false, true><<<nblk, kForceThreads, 0, st>>>(a);
 }
 
 template <bool MIXED>
@@ -432,8 +476,13 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
   const unsigned nblk = force_blocks(n);
   const bool mixed = precision == LJMD_MIXED;
   const bool t1 = ntypes == 1;
-#define LJMD_STEP(M, T) \
-  k_force_full<M, T, true, kUnroll, true, true><<<nblk, kForceThreads, 0, st>>>(a)
+#define LJMD_STEP(M, T)                                                                     \
+  do {                                                                                      \
+    if (n <= kNarrowAtoms)                                                                  \
+      k_force_full<M, T, true, kUnroll, true, true, false><<<nblk, kForceThreads, 0, st>>>(a); \
+    else                                                                                    \
+      k_force_full<M, T, true, kUnroll, true, true, true><<<nblk, kForceThreads, 0, st>>>(a);  \
+  } while (0)
   if (n > 0) {
     if (mixed) {
       if (t1) LJMD_STEP(true, true); else LJMD_STEP(true, false);

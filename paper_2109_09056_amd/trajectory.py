@@ -17,6 +17,7 @@ packed (eps, sigma) come back in the caller's atom order.
 from __future__ import annotations
 
 import ctypes
+import time
 
 import torch
 
@@ -47,17 +48,28 @@ def run_trajectory(L, x0, v0, types, eps, sigma, steps=20, rc=2.5, skin=0.3, dt=
 
 def backprop_trajectory(L, x0, v0, types, eps, sigma, xref, steps=20, checkpoint_every=5,
                         rc=2.5, skin=0.3, dt=0.005, mass=1.0, precision=FP64, device=None,
-                        verify_recompute=True):
+                        verify_recompute=True, timings=None):
+    """timings: optional dict, filled with host wall times (s) of the forward pass and
+    of the reverse pass (recomputation included), each bracketed by a device sync."""
+
+    def mark():
+        if timings is None:
+            return 0.0
+        torch.cuda.synchronize(sim.device)
+        return time.perf_counter()
+
     sim = _forward_sim(L, x0, v0, types, eps, sigma, rc, skin, dt, mass, precision, steps, device)
     nl = sim.nl
     ids = sim.ids
     xref_s = ops.gather_rows(ids, torch.as_tensor(xref, dtype=torch.float64,
                                                   device=sim.device).contiguous())
     ckpt = {}
+    t0 = mark()
     for k in range(0, steps, checkpoint_every):
         ckpt[k] = (sim.x.clone(), sim.v.clone(), sim.F.clone())
         sim.step(min(checkpoint_every, steps - k), energy=False)
     xT = sim.x.clone()
+    t1 = mark()
     loss, xbar = ops.traj_loss(sim.L, sim.x, xref_s)
     vbar = torch.zeros_like(xbar)
     g = torch.empty_like(xbar)
@@ -91,6 +103,9 @@ def backprop_trajectory(L, x0, v0, types, eps, sigma, xref, steps=20, checkpoint
                 ctypes.byref(box), precision, rc, sim.ntypes, p(sim.eps), p(sim.sigma), sim.n,
                 p(xs[n - s]), p(sim.types), p(nl.nbr), p(nl.nnbr), nl.maxn, p(g), p(xbar),
                 p(geps), p(gsig), 1, p(ws), ws.numel(), stream), "ljmd_force_backward")
+    t2 = mark()
+    if timings is not None:
+        timings.update(forward_s=t1 - t0, reverse_s=t2 - t1)
     return TrajectoryResult(
         loss=loss, gx0=sim.in_caller_order(xbar), gv0=sim.in_caller_order(vbar), geps=geps,
         gsigma=gsig, xT=ops.scatter_rows(ids, xT), recompute_bitwise=recompute_ok, sim=sim)

@@ -373,3 +373,61 @@ def test_500k_steps_properties(dev, big):
     assert np.sqrt((d * d).mean()) < 1e-7 and np.abs(d).max() < 1e-3
     nn = sim.nl.nnbr.to(torch.int64)
     assert int(nn.sum().item()) % 2 == 0
+
+
+def test_wide_indices_17m(dev, orc):
+    """17,006,112 atoms (fcc 162^3 cells): sorted indices above 2^24 take the wide
+    (64-bit) gather addressing.  Sampled rows and forces, several of them above 2^24,
+    against the oracle over all atoms; the fused step against the separate calls."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.Workload("fcc162", 5, cells=162)
+    x = li.positions(w)
+    n = x.shape[0]
+    assert n > (1 << 24)
+    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, kind=ops.FULL, dt=w.dt,
+                   device=dev)
+    sim.load(x, None)
+    rng = np.random.default_rng(1)
+    pos = np.sort(np.concatenate([rng.choice(1 << 24, 16, replace=False),
+                                  rng.choice(np.arange(1 << 24, n), 32, replace=False)]))
+    ids = sim.ids[torch.as_tensor(pos, device=dev)].cpu().numpy()  # original ids
+    order = np.argsort(ids)
+    pos, ids = pos[order], ids[order]
+    p = torch.as_tensor(pos, device=dev)
+    cnt = sim.nl.nnbr[p].to(torch.int64)
+    k = torch.arange(sim.nl.maxn, device=dev)
+    flat = ((p[:, None] >> 6) * sim.nl.maxn + k[None, :]) * 64 + (p[:, None] & 63)
+    ent = sim.nl.nbr.reshape(-1)[flat.clamp(max=sim.nl.nbr.numel() - 1)].to(torch.int64)
+    # slots past a row's count are unused memory: clamp before indexing, keep only :cnt
+    rows = sim.ids[ent.clamp(min=0, max=n - 1)].cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    off, nb = orc.neighbor_lists(x, w.box, w.rlist, sel=ids)
+    for q in range(len(ids)):
+        assert np.array_equal(np.sort(rows[q, :cnt[q]]), nb[off[q]:off[q + 1]]), q
+    Fo, eo, _, _ = orc.forces(x, w.box, w.rc, sel=ids)
+    one = T([1.0], dev, torch.float64)
+    for prec in (ops.MIXED, ops.FP64):
+        F, e, _ = ops.compute_forces(w.box, prec, ops.FULL, w.rc, one, one, sim.x, sim.types,
+                                     sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+        Fs, es = F[p].cpu().numpy(), e[p].cpu().numpy()
+        if prec == ops.FP64:
+            assert (np.linalg.norm(Fs - Fo, axis=1).max()
+                    <= FP64_TOL * np.linalg.norm(Fo, axis=1).max())
+            assert np.abs(es - eo).max() <= FP64_TOL * np.abs(eo).max()
+        else:
+            frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+            assert np.linalg.norm(Fs - Fo, axis=1).max() <= MIXED_F_TOL * frms
+            assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
+        del F, e
+    # fused step == forces + closing kick + opening kick/drift, bitwise, on the wide path
+    v1 = torch.zeros_like(sim.x)
+    xn, F1, ev1 = ops.md_step(w.box, ops.MIXED, w.rc, one, one, sim.x, sim.types, sim.nl.nbr,
+                              sim.nl.nnbr, sim.nl.maxn, w.dt, 1.0, v1, F=torch.empty_like(sim.x))
+    F2, _, ev2 = ops.compute_forces(w.box, ops.MIXED, ops.FULL, w.rc, one, one, sim.x, sim.types,
+                                    sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+    assert torch.equal(F1, F2) and torch.equal(ev1[:7], ev2)
+    x2, v2 = sim.x.clone(), torch.zeros_like(sim.x)
+    ops.integrate(ops.KICK, w.dt, 1.0, w.box, x2, v2, F2)
+    ops.integrate(ops.KICK_DRIFT, w.dt, 1.0, w.box, x2, v2, F2)
+    assert torch.equal(v1, v2) and torch.equal(xn, x2)
