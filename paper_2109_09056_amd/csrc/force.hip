@@ -170,7 +170,7 @@ __device__ __forceinline__ void add_pair(const ForceArgs &a, double xi, double y
 // position gathers, then the U pair evaluations, so several loads are in
 // flight per lane.  Whole groups read their indices at fixed offsets from one
 // row pointer (no per-slot address arithmetic); the last, partial group loads
-// only slots below cnt and repeats the group's first index in the others.
+// indices and positions only for slots below cnt.
 // Slots are visited in row order, so the sums are the same as one slot at a
 // time.  WRAP = false skips the minimum image; the caller only takes that
 // path when every atom of the wavefront is at least rc from all box faces,
@@ -207,10 +207,15 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
     double xj[U], yj[U], zj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double *p = pos_of<WIDE>(a.x, j[u]);
-      xj[u] = p[0];
-      yj[u] = p[1];
-      zj[u] = p[2];
+      xj[u] = xi;
+      yj[u] = yi;
+      zj[u] = zi;
+      if (k + u < cnt) {  // no gathers for the padding slots
+        const double *p = pos_of<WIDE>(a.x, j[u]);
+        xj[u] = p[0];
+        yj[u] = p[1];
+        zj[u] = p[2];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -20,6 +20,7 @@ namespace {
 
 constexpr int kSlots = 12;  // register slots: up to 768 candidates staged
 constexpr int kBatch = 16;  // home atoms whose rows are buffered in LDS at once
+constexpr int kFlushRows = kWave / kBatch;  // list rows of a batch written per store instruction
 constexpr int kRowCap = 128;              // longest row buffered in LDS
 constexpr int kRowStride = kRowCap + 1;   // odd stride: lanes reading row k hit distinct banks
 
@@ -169,23 +170,24 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
           base += (int32_t)__popcll(m);
         }
       }
-      const int32_t kept = base < maxn ? base : maxn;
-      if (lane == 0) {
-        nnbr[i] = kept;
-        rowcnt[bi] = kept;
-      }
+      if (lane == 0) rowcnt[bi] = base < maxn ? base : maxn;
       maxc = base > maxc ? base : maxc;
     }
+    __syncthreads();  // rowbuf / rowcnt written by other lanes of this one-wavefront block
+    if (lane < nb) nnbr[b0 + lane] = rowcnt[lane];
     if (buffered) {
-      __syncthreads();  // rowbuf / rowcnt written by other lanes of this one-wavefront block
-      const int32_t mine = lane < nb ? rowcnt[lane] : 0;
+      // lane (a, h) = (lane % kBatch, lane / kBatch) stores rows k = h, h + kFlushRows,
+      // ... of batch atom a: every store instruction covers kFlushRows list rows of
+      // the whole batch
+      const int a = lane % kBatch;
+      const int32_t mine = a < nb ? rowcnt[a] : 0;
       const int32_t kmax = wave_max(mine);
-      const int32_t i = b0 + lane;
+      const int32_t i = b0 + a;
       int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
-      for (int32_t k = 0; k < kmax; ++k)
-        if (k < mine) row[(int64_t)k * kWave] = rowbuf[lane * kRowStride + k];
-      __syncthreads();  // before the next batch overwrites rowbuf
+      for (int32_t k = lane / kBatch; k < kmax; k += kFlushRows)
+        if (k < mine) row[(int64_t)k * kWave] = rowbuf[a * kRowStride + k];
     }
+    __syncthreads();  // before the next batch overwrites rowbuf / rowcnt
   }
 }
 

@@ -220,9 +220,9 @@ class LJSim:
         (the per-atom energy only when energy is true).
 
         FULL lists run one fused launch per step (ljmd_md_step); HALF lists run the
-        separate force and integration calls.  force_events: optional iterator of
-        pre-created (start, end) timing events, recorded on the current stream
-        around every force launch.  graphs: replay the steps between two rebuilds
+        separate force and integration calls.  force_events: optional iterator with
+        one item per step, a pre-created (start, end) timing-event pair recorded
+        on the current stream around that step's force launch, or None.  graphs: replay the steps between two rebuilds
         as one captured HIP graph (FULL lists, no timing events; bitwise the same
         trajectory as launching them one by one).  on_positions: optional callable
         given, for every step in order, the positions tensor the force call of that
@@ -254,11 +254,11 @@ class LJSim:
                 continue
             last = s == nsteps - 1
             args = self._fused_args(energy)[1 if last else 0]
-            if force_events is not None:
-                a, b = next(force_events)
-                a.record()
+            ab = next(force_events) if force_events is not None else None
+            if ab is not None:
+                ab[0].record()
                 _lib.check(mdstep(*args), "ljmd_md_step")
-                b.record()
+                ab[1].record()
             else:
                 _lib.check(mdstep(*args), "ljmd_md_step")
             if on_positions is not None:
@@ -278,11 +278,11 @@ class LJSim:
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
                 kd, fc, kk, kkd = self._step_args(energy)
-            if force_events is not None:
-                a, b = next(force_events)
-                a.record()
+            ab = next(force_events) if force_events is not None else None
+            if ab is not None:
+                ab[0].record()
                 _lib.check(forces(*fc), "ljmd_compute_forces")
-                b.record()
+                ab[1].record()
             else:
                 _lib.check(forces(*fc), "ljmd_compute_forces")
             if on_positions is not None:
