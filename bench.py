@@ -25,9 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per dispatch of the force kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
-# scaled by the copy-kernel calibration; None until counters are taken for this kernel.
-FORCE_TRAFFIC = None
+# Counter figures of the fused step kernel k_force_full<mixed, one type, EV, 8, interior,
+# step, narrow> on the 500,000-atom workload, from the rocprofv3 summaries committed in
+# profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
+# HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
+# gives the two counters); set to None whenever the kernel changes until re-measured.
+FORCE_TRAFFIC = 231.29e6
+FORCE_VALU_BUSY = 0.461
+FORCE_TA_BUSY = 0.756
 
 
 def log(msg):
@@ -241,7 +246,9 @@ def main():
                      "kernel": "k_force_full<mixed, step> fused force+integration "
                                "(+ energy/virial/KE column sum)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": FORCE_TRAFFIC,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(FORCE_TRAFFIC) if FORCE_TRAFFIC else None,
+                     "valu_busy": FORCE_VALU_BUSY, "texture_addr_busy": FORCE_TA_BUSY,
                      "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
     }
     if not args.no_extras:
