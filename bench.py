@@ -260,6 +260,18 @@ def main():
         log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
         line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),
                            "trajectory_256k": bwd_fwd_trajectory(dev)}
+        w2 = li.WORKLOADS["lj2m"]
+        s2 = li.make_system(w2)
+        t2, f2ms, sim2 = md_run(w2, s2, ops.MIXED, w2.steps, 40, dev)
+        nb2 = float(sim2.nl.nnbr.double().mean().item())
+        line["scale_2m"] = {"natoms": w2.natoms, "steps": w2.steps,
+                            "value": round(w2.natoms * w2.steps / t2, 1), "unit": "atom-steps/s",
+                            "ms_per_step": round(t2 * 1e3 / w2.steps, 5),
+                            "step_launch_us": round(statistics.mean(f2ms) * 1e3, 3),
+                            "achieved_GBps": round(w2.natoms * (4.0 * nb2 + 132) /
+                                                   (statistics.mean(f2ms) * 1e-3) / 1e9, 2)}
+        log(f"[bench] 2M atoms: {t2 * 1e3 / w2.steps:.4f} ms/step")
+        del sim2, s2
         log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")

@@ -65,6 +65,9 @@ WORKLOADS = {
     "lj32k_fm": Workload("lj32k_fm", 3, cells=20, ntypes=2),
     "lj256k_traj": Workload("lj256k_traj", 4, cells=40, steps=20, ntypes=2,
                             checkpoint_every=5),
+    # the same liquid at 2,048,000 atoms: a working set well beyond the 256 MiB
+    # Infinity Cache (the uncached-HBM regime of the 500k benchmark)
+    "lj2m": Workload("lj2m", 6, cells=80, steps=200),
 }
 
 

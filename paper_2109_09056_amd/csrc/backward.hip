@@ -14,6 +14,8 @@
 // accumulated per lane by the neighbor's type, reduced per block by the
 // lane's own type in a fixed order, and summed over blocks by one column-sum
 // launch: the whole adjoint is bitwise reproducible.
+#include <type_traits>
+
 #include "common.h"
 
 namespace ljmd {
@@ -25,7 +27,7 @@ constexpr int kWaves = kThreads / kWave;
 
 struct BwdArgs {
   BoxK b;
-  double rc2;
+  double rc, rc2;
   int32_t ntypes;
   const double *eps;
   const double *sig;
@@ -83,7 +85,7 @@ __device__ __forceinline__ PairB pair_b(double r2, const BCoef &c) {
 
 // TT: 1 or 2 types with register accumulators; 0: any T <= LJMD_MAX_TYPES with
 // lane-private LDS columns.
-template <bool MIXED, int TT>
+template <bool MIXED, int TT, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
   constexpr int MT = LJMD_MAX_TYPES;
   __shared__ double tab[(TT == 1 ? 1 : MT * MT) * 7];
@@ -110,40 +112,35 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
 #pragma unroll
   for (int q = 0; q < (TT == 0 ? 1 : TT); ++q) ge[q] = gs[q] = 0.0;
   int ti = 0;
-  if (i < a.n) {
-    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
-                 zi = a.x[3 * (int64_t)i + 2];
+  const bool live = i < a.n;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = a.x[3 * (int64_t)i];
+    yi = a.x[3 * (int64_t)i + 1];
+    zi = a.x[3 * (int64_t)i + 2];
+  }
+  // wavefront-uniform: every atom of the wavefront at least rc from all faces
+  // (then the raw displacement is the minimum image for every pair inside rc)
+  const bool in = !live || (xi >= a.rc && xi <= a.b.L[0] - a.rc && yi >= a.rc &&
+                            yi <= a.b.L[1] - a.rc && zi >= a.rc && zi <= a.b.L[2] - a.rc);
+  const bool interior = __ballot(!in) == 0;
+  if (live) {
     const double gxi = a.g[3 * (int64_t)i], gyi = a.g[3 * (int64_t)i + 1],
                  gzi = a.g[3 * (int64_t)i + 2];
     ti = TT == 1 ? 0 : a.type[i];
     const int32_t cnt = a.nnbr[i];
     const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
-    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
-    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
     double ax = 0.0, ay = 0.0, az = 0.0;
-    // U slots per iteration: all index loads, then all gathers of x_j and g_j,
-    // then the U pair evaluations (several loads in flight per lane).
-    constexpr int U = 4;
-    for (int32_t k0 = 0; k0 < cnt; k0 += U) {
-      int32_t jj[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) jj[u] = row[(int64_t)((u == 0 || k0 + u < cnt) ? k0 + u : k0) * kWave];
-      double xj[U][3], gj[U][3];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          xj[u][q] = a.x[3 * (int64_t)jj[u] + q];
-          gj[u][q] = a.g[3 * (int64_t)jj[u] + q];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-      const int32_t j = jj[u];
-      const double dx = min_image(xi - xj[u][0], L0, iL0);
-      const double dy = min_image(yi - xj[u][1], L1, iL1);
-      const double dz = min_image(zi - xj[u][2], L2, iL2);
+    // one list entry: j with its position and cotangent
+    auto entry = [&](auto wrap, int32_t j, const double *xj, const double *gj, bool valid) {
+      double dx = xi - xj[0], dy = yi - xj[1], dz = zi - xj[2];
+      if constexpr (decltype(wrap)::value) {
+        dx = min_image(dx, a.b.L[0], a.b.invL[0]);
+        dy = min_image(dy, a.b.L[1], a.b.invL[1]);
+        dz = min_image(dz, a.b.L[2], a.b.invL[2]);
+      }
       const double r2 = dist2(dx, dy, dz);
-      if ((u == 0 || k0 + u < cnt) && r2 < a.rc2) {
+      if (valid && r2 < a.rc2) {
         int tj = 0;
         BCoef c;
         if constexpr (TT == 1) {
@@ -154,9 +151,9 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
           c = BCoef{t[0], t[1], t[2], t[3], t[4], t[5], t[6]};
         }
         const PairB p = pair_b<MIXED>(r2, c);
-        const double dgx = gxi - gj[u][0];
-        const double dgy = gyi - gj[u][1];
-        const double dgz = gzi - gj[u][2];
+        const double dgx = gxi - gj[0];
+        const double dgy = gyi - gj[1];
+        const double dgz = gzi - gj[2];
         const double ddg = __builtin_fma(dx, dgx, __builtin_fma(dy, dgy, dz * dgz));
         const double q = 2.0 * p.sp * ddg;
         ax = __builtin_fma(p.s, dgx, __builtin_fma(q, dx, ax));
@@ -181,8 +178,61 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
           col[MT + tj] = __builtin_fma(gid, p.dss, col[MT + tj]);
         }
       }
+    };
+    // Groups of U slots: the U index loads, then the gathers of x_j and g_j, then
+    // the U entries.  Whole groups read indices at fixed offsets from one row
+    // pointer; the last, partial group gathers only slots below cnt.  Row order
+    // throughout, so the sums match one slot at a time.
+    auto walk = [&](auto wrap) {
+      constexpr int U = 4;
+      const int32_t whole = cnt - cnt % U;
+      const int32_t *rp = row;
+      int32_t k = 0;
+      for (; k < whole; k += U, rp += U * kWave) {
+        int32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = rp[u * kWave];
+        double xj[U][3], gj[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double *px = pos_of<WIDE>(a.x, jj[u]);
+          const double *pg = pos_of<WIDE>(a.g, jj[u]);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            xj[u][q] = px[q];
+            gj[u][q] = pg[q];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) entry(wrap, jj[u], xj[u], gj[u], true);
       }
-    }
+      if (k < cnt) {
+        int32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = rp[(k + u < cnt ? u : 0) * kWave];
+        double xj[U][3], gj[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) xj[u][q] = gj[u][q] = 0.0;
+          if (k + u < cnt) {
+            const double *px = pos_of<WIDE>(a.x, jj[u]);
+            const double *pg = pos_of<WIDE>(a.g, jj[u]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              xj[u][q] = px[q];
+              gj[u][q] = pg[q];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) entry(wrap, jj[u], xj[u], gj[u], k + u < cnt);
+      }
+    };
+    if (interior)
+      walk(std::false_type{});
+    else
+      walk(std::true_type{});
     double *o = a.gx + 3 * (int64_t)i;
     if (a.accumulate) {
       o[0] += ax;
@@ -267,6 +317,7 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
                     hipStream_t st) {
   BwdArgs a;
   a.b = b;
+  a.rc = rc;
   a.rc2 = rc * rc;
   a.ntypes = ntypes;
   a.eps = eps;
@@ -287,7 +338,13 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
   const int stride = a.stride;
   double *colsums = a.partial + (size_t)nblk * stride;
   const bool mixed = precision == LJMD_MIXED;
-#define LJMD_VJP(M, TT) k_vjp<M, TT><<<nblk, kThreads, 0, st>>>(a)
+#define LJMD_VJP(M, TT)                                \
+  do {                                                 \
+    if (n <= kNarrowAtoms)                             \
+      k_vjp<M, TT, false><<<nblk, kThreads, 0, st>>>(a); \
+    else                                               \
+      k_vjp<M, TT, true><<<nblk, kThreads, 0, st>>>(a);  \
+  } while (0)
   if (ntypes == 1) {
     if (mixed) LJMD_VJP(true, 1); else LJMD_VJP(false, 1);
   } else if (ntypes == 2) {

@@ -32,6 +32,18 @@ __device__ __forceinline__ double min_image(double d, double L, double invL) {
   return __builtin_fma(-k, L, d);
 }
 
+// Atom j's 3-vector in an [n][3] FP64 array.  Narrow form (every index below
+// kNarrowAtoms): a 32-bit byte offset from the array base, formed with the
+// full-rate 24-bit multiply; wide form: 64-bit index arithmetic.
+constexpr int64_t kNarrowAtoms = int64_t(1) << 24;
+template <bool WIDE>
+__device__ __forceinline__ const double *pos_of(const double *x, int32_t j) {
+  if constexpr (WIDE)
+    return x + 3 * (int64_t)j;
+  else
+    return (const double *)((const char *)x + __umul24((uint32_t)j, 24u));
+}
+
 // r^2 in the fixed order (dx*dx + dy*dy) + dz*dz; the library is compiled
 // with -ffp-contract=off so no FMA is formed here.
 __device__ __forceinline__ double dist2(double dx, double dy, double dz) {

@@ -118,17 +118,6 @@ struct Acc {
   double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
 };
 
-// Address of atom j's position.  Narrow form (every index below 2^24): a
-// 32-bit byte offset from the array base, formed with the full-rate 24-bit
-// multiply; wide form: 64-bit index arithmetic.
-template <bool WIDE>
-__device__ __forceinline__ const double *pos_of(const double *x, int32_t j) {
-  if constexpr (WIDE)
-    return x + 3 * (int64_t)j;
-  else
-    return (const double *)((const char *)x + __umul24((uint32_t)j, 24u));
-}
-
 // One neighbor j of atom i: minimum image (WRAP), cutoff test, pair force and
 // the row's accumulators.  `valid` is false for padding slots of a short group.
 template <bool MIXED, bool T1, bool EV, bool WRAP>
@@ -380,9 +369,6 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
 // Full-list loop shape: 8 slots per iteration with the exact interior fast
 // path (measured best on MI355X against 1, 2 and 4 slots, with and without it).
 constexpr int kUnroll = 8;
-
-// Indices below 2^24 take the narrow (32-bit offset) gather addressing.
-constexpr int64_t kNarrowAtoms = int64_t(1) << 24;
 
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {

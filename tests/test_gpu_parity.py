@@ -431,3 +431,35 @@ def test_wide_indices_17m(dev, orc):
     ops.integrate(ops.KICK, w.dt, 1.0, w.box, x2, v2, F2)
     ops.integrate(ops.KICK_DRIFT, w.dt, 1.0, w.box, x2, v2, F2)
     assert torch.equal(v1, v2) and torch.equal(xn, x2)
+    del xn, F1, F2, v1, v2, x2
+    # adjoint on the wide path (FP64): directional derivatives of g.F by central
+    # differences, along a displacement of 64 atoms (half of them above 2^24) and
+    # along eps and sigma; the pair set is fixed (no moved pair within 1e-4 of rc)
+    h = 1e-6
+    g = torch.as_tensor(np.random.default_rng(2).normal(size=(n, 3)), device=dev)
+    gx, geps, gsig = ops.force_backward(w.box, ops.FP64, w.rc, one, one, sim.x, sim.types,
+                                        sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn, g)
+    moved = np.sort(np.concatenate([rng.choice(1 << 24, 32, replace=False),
+                                    rng.choice(np.arange(1 << 24, n), 32, replace=False)]))
+    mids = sim.ids[torch.as_tensor(moved, device=dev)].cpu().numpy()
+    mo = np.argsort(mids)
+    off2, nb2 = orc.neighbor_lists(x, w.box, w.rlist, sel=mids[mo])
+    for q, a_ in enumerate(mids[mo]):
+        d = x[nb2[off2[q]:off2[q + 1]]] - x[a_]
+        d -= w.box * np.round(d / w.box)
+        assert np.abs(np.sqrt((d * d).sum(1)) - w.rc).min() > 1e-4
+    wdir = torch.zeros_like(sim.x)
+    wdir[torch.as_tensor(moved, device=dev)] = torch.as_tensor(
+        np.random.default_rng(3).normal(size=(len(moved), 3)), device=dev)
+
+    def gF(xx, e=one, sg=one):
+        F, _, _ = ops.compute_forces(w.box, ops.FP64, ops.FULL, w.rc, e, sg, xx, sim.types,
+                                     sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn, want_energy=False)
+        return float((g * F).sum().item())
+
+    fd = (gF(sim.x + h * wdir) - gF(sim.x - h * wdir)) / (2 * h)
+    assert fd == pytest.approx(float((wdir * gx).sum().item()), rel=1e-5)
+    fe = (gF(sim.x, e=one * (1 + h)) - gF(sim.x, e=one * (1 - h))) / (2 * h)
+    assert fe == pytest.approx(float(geps.item()), rel=1e-6)
+    fs = (gF(sim.x, sg=one * (1 + h)) - gF(sim.x, sg=one * (1 - h))) / (2 * h)
+    assert fs == pytest.approx(float(gsig.item()), rel=1e-5)
