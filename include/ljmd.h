@@ -15,6 +15,7 @@
  *   ljmd_build_neighbors  Verlet lists over the 27-cell stencil (full or half)
  *   ljmd_compute_forces   12-6 LJ forces, per-atom energy, energy + virial
  *   ljmd_integrate        velocity-Verlet half kick + drift + wrap / half kick
+ *   ljmd_md_step          forces and both half kicks + drift of one step, fused
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
  *
  * plus a few helpers (grid, workspace sizes, errors) and the elementwise
