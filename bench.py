@@ -20,6 +20,7 @@ import os
 import statistics
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -178,6 +179,33 @@ def bwd_fwd_trajectory(dev):
             "kernel_ratio": round(tb / tf, 3)}
 
 
+def shard_share(dev, steps=200, warmup=40):
+    """One GPU's share of the 500,000-atom box split 2x2x2 over eight GPUs: the owned
+    brick (edge L/2) plus its ghost shell of thickness rlist, cut from the same input
+    and placed in a periodic box with an empty gap >= rlist, so that no pair reaches
+    across the boundary.  Ghost rows are computed too (no owned-only launch exists),
+    and ghosts move without exchange: a timing of the kernels at the shard's shape."""
+    import numpy as np
+    import lj_inputs as li
+    from paper_2109_09056_amd import ops
+    w = li.WORKLOADS["lj500k"]
+    s = li.make_system(w)
+    L, rl = w.box, w.rlist
+    xs = np.mod(s["x"] + rl, L)  # owned brick -> [rl, L/2 + rl) per dimension
+    keep = np.all(xs < L / 2 + 2 * rl, axis=1)
+    owned = np.all((xs >= rl) & (xs < L / 2 + rl), axis=1)
+    edge = L / 2 + 3 * rl
+    sub = {"x": np.ascontiguousarray(xs[keep]), "v": np.ascontiguousarray(s["v"][keep])}
+    shard = types.SimpleNamespace(box=edge, rc=w.rc, skin=w.skin, dt=w.dt,
+                                  rebuild_every=w.rebuild_every)
+    t, fms, sim = md_run(shard, sub, ops.MIXED, steps, warmup, dev)
+    n_all, n_own = int(keep.sum()), int(owned.sum())
+    return {"owned_atoms": n_own, "ghost_atoms": n_all - n_own, "box_edge": round(float(edge[0]), 4),
+            "steps": steps, "ms_per_step": round(t * 1e3 / steps, 5),
+            "owned_atom_steps_per_s": round(n_own * steps / t, 1),
+            "step_launch_us": round(statistics.mean(fms) * 1e3, 3)}
+
+
 def cpu_baseline(w, s, target_s):
     """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input."""
     import numpy as np
@@ -272,6 +300,8 @@ def main():
                                                    (statistics.mean(f2ms) * 1e-3) / 1e9, 2)}
         log(f"[bench] 2M atoms: {t2 * 1e3 / w2.steps:.4f} ms/step")
         del sim2, s2
+        line["shard_share_2x2x2"] = shard_share(dev)
+        log(f"[bench] one 2x2x2 shard: {line['shard_share_2x2x2']}")
         log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
