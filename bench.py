@@ -179,6 +179,35 @@ def bwd_fwd_trajectory(dev):
             "kernel_ratio": round(tb / tf, 3)}
 
 
+def mixed_error(w, sim):
+    """Mixed against FP64 forces and energies at the final positions of the mixed run."""
+    import torch
+    from paper_2109_09056_amd import ops
+    out = {}
+    for name, prec in (("mixed", ops.MIXED), ("fp64", ops.FP64)):
+        out[name] = ops.compute_forces(w.box, prec, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x,
+                                       sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+    (Fm, em, evm), (Fd, ed, evd) = out["mixed"], out["fp64"]
+    frms = torch.sqrt((Fd * Fd).sum(dim=1).mean())
+    return {"max_dF_over_Frms": float((Fm - Fd).norm(dim=1).max() / frms),
+            "max_rel_de_atom": float(((em - ed).abs() / ed.abs()).max()),
+            "max_de_atom_over_mean_abs_e": float((em - ed).abs().max() / ed.abs().mean()),
+            "atoms_rel_de_above_1e-6": int(((em - ed).abs() > 1e-6 * ed.abs()).sum()),
+            "rel_dE": float(abs((evm[0] - evd[0]) / evd[0])),
+            "max_rel_dW": float(((evm[1:] - evd[1:]).abs().max() / evd[1:].abs().max()))}
+
+
+def rebuild_time(sim, reps=20):
+    """Average wall time of one re-sort + list build (bin, build, overflow check)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.rebuild()
+    torch.cuda.synchronize()
+    return round((time.perf_counter() - t0) / reps * 1e6, 2)
+
+
 def shard_share(dev, steps=200, warmup=40):
     """One GPU's share of the 500,000-atom box split 2x2x2 over eight GPUs: the owned
     brick (edge L/2) plus its ghost shell of thickness rlist, cut from the same input
@@ -286,6 +315,8 @@ def main():
                         "step_launch_us": round(statistics.mean(f64ms) * 1e3, 3),
                         "mixed_over_fp64": round(t64 / t_mixed, 4)}
         log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
+        line["fp64"]["mixed_error_vs_fp64"] = mixed_error(w, sim)
+        line["rebuild_us"] = rebuild_time(sim)
         line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),
                            "trajectory_256k": bwd_fwd_trajectory(dev)}
         w2 = li.WORKLOADS["lj2m"]
