@@ -57,8 +57,10 @@ extern "C" {
 
 /* ---- enums ---- */
 #define LJMD_FP64 0   /* all pair arithmetic in FP64 */
-#define LJMD_MIXED 1  /* FP64 displacement, r^2 and cutoff test; FP32 pair math;
-                         FP64 accumulation of forces, energies, virial, gradients */
+#define LJMD_MIXED 1  /* FP64 displacement, r^2 and cutoff test; FP32 pair math
+                         (the pair energy: FP64 from the FP32 reciprocal after one
+                         FP64 Newton step); FP64 accumulation of forces, energies,
+                         virial, gradients */
 #define LJMD_FULL 0   /* every ordered pair (i, j): each atom owns all its neighbors */
 #define LJMD_HALF 1   /* each unordered pair once, owned by the lower sorted index */
 #define LJMD_KICK_DRIFT 0 /* v += dt/2 F/m; x += dt v; wrap x into [0, L) */

@@ -9,9 +9,10 @@
 //   u   = sr6 (4 eps sr6 - 4 eps)
 // FP64 form: all of it in FP64 (reciprocal = hardware estimate + two Newton
 // steps).  Mixed form: displacement, r^2 and the cutoff test in FP64 (so the
-// pair set is the FP64 one), then ri2, sr6 and the pair scalars s and u in
-// FP32; s and u are promoted once, and the pair force s*d (with the FP64 d)
-// and the accumulation of F, e, E and W are FP64.
+// pair set is the FP64 one), then ri2, sr6 and the force scalar s in FP32; s
+// is promoted once, and the pair force s*d (with the FP64 d) and the
+// accumulation of F, e, E and W are FP64.  The pair energy u is taken in
+// FP64 from the FP32 reciprocal refined by one FP64 Newton step.
 //
 // FULL list: lane i of the grid owns atom i and walks its row of the tile
 // (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l], one coalesced
@@ -98,7 +99,17 @@ __device__ __forceinline__ PairOut lj_pair(double dx, double dy, double dz, doub
     o.fx = s * dx;
     o.fy = s * dy;
     o.fz = s * dz;
-    if constexpr (EV) o.u = (double)(sr6 * __builtin_fmaf((float)c.e4, sr6, -(float)c.e4));
+    if constexpr (EV) {
+      // The pair energy changes sign at r = sigma, and a per-atom energy can
+      // nearly cancel; an FP32 u would leave such atoms with relative errors
+      // far above the FP32 rounding.  u is formed in FP64 from the FP32
+      // reciprocal after one FP64 Newton step (relative error ~1e-13).
+      const double y0 = (double)ri2;
+      const double y = __builtin_fma(y0, __builtin_fma(-r2, y0, 1.0), y0);
+      const double s2 = c.sig2 * y;
+      const double s6 = s2 * s2 * s2;
+      o.u = s6 * __builtin_fma(c.e4, s6, -c.e4);
+    }
   } else {
     const double ri2 = recip64(r2);
     const double sr2 = c.sig2 * ri2;

@@ -349,9 +349,10 @@ def test_500k_sampled_neighbors_and_forces(dev, orc, big):
             assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
 
 
-def test_500k_steps_properties(dev, big):
+def test_500k_steps_properties(dev, orc, big):
     """40 steps (two rebuilds) at 500k: momentum stays zero, mixed and FP64 runs from the
-    same start stay together, and the full list stays symmetric."""
+    same start stay together, the full list stays symmetric, and at the evolved positions
+    sampled forces and energies of both precisions match the oracle."""
     import torch
     from paper_2109_09056_amd import md, ops
     w, s, sim = big
@@ -373,6 +374,24 @@ def test_500k_steps_properties(dev, big):
     assert np.sqrt((d * d).mean()) < 1e-7 and np.abs(d).max() < 1e-3
     nn = sim.nl.nnbr.to(torch.int64)
     assert int(nn.sum().item()) % 2 == 0
+    # snapshot parity at the evolved positions: sampled atoms against the oracle
+    atoms = np.sort(np.random.default_rng(4).choice(w.natoms, 300, replace=False))
+    Fo, eo, _, _ = orc.forces(xm, w.box, w.rc, sel=atoms)
+    ids = sim.ids.cpu().numpy()
+    pos_of = np.empty(w.natoms, dtype=np.int64)
+    pos_of[ids] = np.arange(w.natoms)
+    for prec in (ops.MIXED, ops.FP64):
+        F, e, _ = ops.compute_forces(w.box, prec, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x,
+                                     sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+        Fs, es = F.cpu().numpy()[pos_of[atoms]], e.cpu().numpy()[pos_of[atoms]]
+        if prec == ops.FP64:
+            assert (np.linalg.norm(Fs - Fo, axis=1).max()
+                    <= FP64_TOL * np.linalg.norm(Fo, axis=1).max())
+            assert np.abs(es - eo).max() <= FP64_TOL * np.abs(eo).max()
+        else:
+            frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+            assert np.linalg.norm(Fs - Fo, axis=1).max() <= MIXED_F_TOL * frms
+            assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
 
 
 def test_wide_indices_17m(dev, orc):
