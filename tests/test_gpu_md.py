@@ -213,3 +213,34 @@ def test_graph_replay_matches_eager(dev, prec):
     for (xa, va, fa, ea), (xb, vb, fb, eb) in zip(*runs):
         assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(fa, fb)
         assert torch.equal(ea, eb)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_forces_at_oracle_snapshot(dev, orc, oracle_32k_run, prec):
+    """Every atom's force and energy, and E and W, at the oracle's own step-100 positions of
+    the 32,000-atom run (the lattice melting into a liquid), against the oracle there."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w, s, thermo, snaps = oracle_32k_run
+    x = snaps[100][0]
+    Fo, eo, Wo, _ = orc.forces(x, w.box, w.rc)
+    Eo = eo.sum()
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    sim = md.LJSim(w.box, precision=P, device=dev)
+    sim.load(x, None)
+    F, e, ev = ops.compute_forces(w.box, P, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x,
+                                  sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
+    Fg = sim.in_caller_order(F).cpu().numpy()
+    eg = sim.in_caller_order(e.reshape(-1, 1)).cpu().numpy().reshape(-1)
+    ev = ev.cpu().numpy()
+    if P == ops.FP64:
+        assert np.linalg.norm(Fg - Fo, axis=1).max() <= 1e-12 * np.linalg.norm(Fo, axis=1).max()
+        assert np.abs(eg - eo).max() <= 1e-12 * np.abs(eo).max()
+        assert ev[0] == pytest.approx(Eo, rel=1e-12)
+        assert np.abs(ev[1:] - Wo).max() <= 1e-12 * np.abs(Wo).max()
+    else:
+        frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+        assert np.linalg.norm(Fg - Fo, axis=1).max() <= 1e-5 * frms
+        assert (np.abs(eg - eo) / np.abs(eo)).max() <= 1e-6
+        assert ev[0] == pytest.approx(Eo, rel=1e-6)
+        assert np.abs(ev[1:] - Wo).max() <= 1e-6 * np.abs(Wo).max()

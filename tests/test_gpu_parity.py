@@ -349,10 +349,9 @@ def test_500k_sampled_neighbors_and_forces(dev, orc, big):
             assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
 
 
-def test_500k_steps_properties(dev, orc, big):
+def test_500k_steps_properties(dev, big):
     """40 steps (two rebuilds) at 500k: momentum stays zero, mixed and FP64 runs from the
-    same start stay together, the full list stays symmetric, and at the evolved positions
-    sampled forces and energies of both precisions match the oracle."""
+    same start stay together, and the full list stays symmetric."""
     import torch
     from paper_2109_09056_amd import md, ops
     w, s, sim = big
@@ -374,24 +373,6 @@ def test_500k_steps_properties(dev, orc, big):
     assert np.sqrt((d * d).mean()) < 1e-7 and np.abs(d).max() < 1e-3
     nn = sim.nl.nnbr.to(torch.int64)
     assert int(nn.sum().item()) % 2 == 0
-    # snapshot parity at the evolved positions: sampled atoms against the oracle
-    atoms = np.sort(np.random.default_rng(4).choice(w.natoms, 300, replace=False))
-    Fo, eo, _, _ = orc.forces(xm, w.box, w.rc, sel=atoms)
-    ids = sim.ids.cpu().numpy()
-    pos_of = np.empty(w.natoms, dtype=np.int64)
-    pos_of[ids] = np.arange(w.natoms)
-    for prec in (ops.MIXED, ops.FP64):
-        F, e, _ = ops.compute_forces(w.box, prec, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x,
-                                     sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
-        Fs, es = F.cpu().numpy()[pos_of[atoms]], e.cpu().numpy()[pos_of[atoms]]
-        if prec == ops.FP64:
-            assert (np.linalg.norm(Fs - Fo, axis=1).max()
-                    <= FP64_TOL * np.linalg.norm(Fo, axis=1).max())
-            assert np.abs(es - eo).max() <= FP64_TOL * np.abs(eo).max()
-        else:
-            frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
-            assert np.linalg.norm(Fs - Fo, axis=1).max() <= MIXED_F_TOL * frms
-            assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
 
 
 def test_wide_indices_17m(dev, orc):
@@ -407,13 +388,20 @@ def test_wide_indices_17m(dev, orc):
     sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, kind=ops.FULL, dt=w.dt,
                    device=dev)
     sim.load(x, None)
+    # samples chosen from the generator's positions: atoms of the top cell layer in z
+    # sort last (cell-major order), so their sorted indices lie above 2^24
+    nc = orc.grid(w.box, w.rlist)
+    hz = w.box[2] / nc[2]
     rng = np.random.default_rng(1)
-    pos = np.sort(np.concatenate([rng.choice(1 << 24, 16, replace=False),
-                                  rng.choice(np.arange(1 << 24, n), 32, replace=False)]))
-    ids = sim.ids[torch.as_tensor(pos, device=dev)].cpu().numpy()  # original ids
-    order = np.argsort(ids)
-    pos, ids = pos[order], ids[order]
-    p = torch.as_tensor(pos, device=dev)
+    top = np.nonzero(x[:, 2] >= (nc[2] - 1) * hz * (1 + 1e-12))[0]
+    ids = np.sort(np.concatenate([rng.choice(n, 16, replace=False),
+                                  rng.choice(top, 32, replace=False)]))
+    ids = np.unique(ids)
+    inv = torch.empty(n, dtype=torch.int64, device=dev)
+    inv[sim.ids] = torch.arange(n, device=dev)
+    p = inv[torch.as_tensor(ids, device=dev)]
+    pos = p.cpu().numpy()
+    assert (pos >= (1 << 24)).sum() >= 32
     cnt = sim.nl.nnbr[p].to(torch.int64)
     k = torch.arange(sim.nl.maxn, device=dev)
     flat = ((p[:, None] >> 6) * sim.nl.maxn + k[None, :]) * 64 + (p[:, None] & 63)
@@ -458,18 +446,18 @@ def test_wide_indices_17m(dev, orc):
     g = torch.as_tensor(np.random.default_rng(2).normal(size=(n, 3)), device=dev)
     gx, geps, gsig = ops.force_backward(w.box, ops.FP64, w.rc, one, one, sim.x, sim.types,
                                         sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn, g)
-    moved = np.sort(np.concatenate([rng.choice(1 << 24, 32, replace=False),
-                                    rng.choice(np.arange(1 << 24, n), 32, replace=False)]))
-    mids = sim.ids[torch.as_tensor(moved, device=dev)].cpu().numpy()
-    mo = np.argsort(mids)
-    off2, nb2 = orc.neighbor_lists(x, w.box, w.rlist, sel=mids[mo])
-    for q, a_ in enumerate(mids[mo]):
+    mids = np.unique(np.concatenate([rng.choice(n, 32, replace=False),
+                                     rng.choice(top, 32, replace=False)]))
+    off2, nb2 = orc.neighbor_lists(x, w.box, w.rlist, sel=mids)
+    for q, a_ in enumerate(mids):
         d = x[nb2[off2[q]:off2[q + 1]]] - x[a_]
         d -= w.box * np.round(d / w.box)
         assert np.abs(np.sqrt((d * d).sum(1)) - w.rc).min() > 1e-4
+    moved = inv[torch.as_tensor(mids, device=dev)]
+    assert int((moved >= (1 << 24)).sum()) >= 32
     wdir = torch.zeros_like(sim.x)
-    wdir[torch.as_tensor(moved, device=dev)] = torch.as_tensor(
-        np.random.default_rng(3).normal(size=(len(moved), 3)), device=dev)
+    wdir[moved] = torch.as_tensor(np.random.default_rng(3).normal(size=(len(mids), 3)),
+                                  device=dev)
 
     def gF(xx, e=one, sg=one):
         F, _, _ = ops.compute_forces(w.box, ops.FP64, ops.FULL, w.rc, e, sg, xx, sim.types,
