@@ -94,8 +94,9 @@ __device__ __forceinline__ int32_t locate(int32_t t, const int32_t *rs, const in
   return rs[r] + (t - pre[r]);
 }
 
-// Register-staged build of one cell's rows (candidates <= kSlots * 64).
-template <bool HALF, bool WRAP>
+// Register-staged build of one cell's rows (candidates <= kSlots * 64).  BUF:
+// rows are compacted in LDS (maxn <= kRowCap) rather than stored directly.
+template <bool HALF, bool WRAP, bool BUF>
 __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const double *__restrict__ x,
                                              int32_t h0, int32_t h1, int32_t total, int nslot,
                                              const int32_t *rs, const int32_t *pre, int32_t maxn,
@@ -123,7 +124,7 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   // and then written out k by k: the atoms of a batch are consecutive, so each
   // store instruction covers one contiguous run of a tile row instead of
   // scattering 4-byte entries 256 bytes apart.
-  const bool buffered = maxn <= kRowCap;
+  constexpr bool buffered = BUF;
   // home positions: lane l holds atom c0 + l of the current chunk of 64, read
   // back by every lane with a scalar readlane (no load latency per home atom)
   double hx = 0.0, hy = 0.0, hz = 0.0;
@@ -155,7 +156,7 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
           }
           const double r2 = dist2(dx, dy, dz);
           const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
-          const uint64_t m = __ballot(ok);
+          const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
           if (ok) {
             const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
                                          (uint32_t)(m >> 32),
@@ -222,12 +223,15 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
       wrap |= g.nc[k] < 4 || cc[k] == 0 || cc[k] == g.nc[k] - 1;
   }
   if (nslot <= kSlots) {
-    if (wrap)
-      build_staged<HALF, true>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, rowbuf,
-                               rowcnt, maxc);
-    else
-      build_staged<HALF, false>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr,
-                                rowbuf, rowcnt, maxc);
+#define LJMD_STAGED(W, B)                                                                   \
+  build_staged<HALF, W, B>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, rowbuf, \
+                           rowcnt, maxc)
+    if (maxn <= kRowCap) {
+      if (wrap) LJMD_STAGED(true, true); else LJMD_STAGED(false, true);
+    } else {
+      if (wrap) LJMD_STAGED(true, false); else LJMD_STAGED(false, false);
+    }
+#undef LJMD_STAGED
   } else {
     const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
     const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
