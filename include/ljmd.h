@@ -16,6 +16,8 @@
  *   ljmd_compute_forces   12-6 LJ forces, per-atom energy, energy + virial
  *   ljmd_integrate        velocity-Verlet half kick + drift + wrap / half kick
  *   ljmd_md_step          forces and both half kicks + drift of one step, fused
+ *   ljmd_list_to_csr, ljmd_compute_forces_csr
+ *                         compressed list form and team-per-atom traversal
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
  *
  * plus a few helpers (grid, workspace sizes, errors) and the elementwise
@@ -76,9 +78,12 @@ extern "C" {
 #define LJMD_OP_BACKWARD 2
 #define LJMD_OP_INTEGRATE 3
 #define LJMD_OP_LOSS 4
+#define LJMD_OP_CSR 5        /* ljmd_list_to_csr */
+#define LJMD_OP_FORCES_CSR 6 /* ljmd_compute_forces_csr (any team) */
 
 #define LJMD_MAX_TYPES 8
-#define LJMD_TILE 64 /* atoms per neighbor-list tile: one wavefront */
+#define LJMD_TILE 64
+#define LJMD_MAX_TEAM 16 /* largest team (lanes per atom) of ljmd_compute_forces_csr */ /* atoms per neighbor-list tile: one wavefront */
 
 typedef struct {
   double L[3]; /* box edges; periodic in all three dimensions, origin at 0 */
@@ -245,6 +250,41 @@ int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
                  const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
                  int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
                  double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_list_to_csr -- compressed (CSR) copy of a tiled neighbor list (paper:
+ * Cabana stores neighbor lists either compressed -- row offsets plus one flat
+ * index array -- or dense, with a fixed row capacity; "Neighbor List
+ * Creation").  Rows keep their order.
+ *   nbr, nnbr, maxn  a list from ljmd_build_neighbors (rows of min(nnbr, maxn))
+ *   offsets  int64 [n+1] output: row i is csr[offsets[i] .. offsets[i+1])
+ *   csr      int32 [cap] output; entries at positions >= cap are not written,
+ *            so a too-small cap is seen as offsets[n] > cap once the call completes
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_CSR, n, 0, 0)
+ */
+int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                     int64_t *offsets, int32_t *csr, int64_t cap, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * ljmd_compute_forces_csr -- the FULL-list forces of ljmd_compute_forces over a
+ * CSR list (ljmd_list_to_csr of a FULL list), with `team` lanes per atom
+ * (paper: Cabana's hierarchical neighbor traversal -- one thread per particle
+ * or a team of threads per particle; "Parallel Loops").  Lane t of a team takes
+ * row entries t, t + team, ...; the team's sums are combined in a fixed
+ * butterfly order, so results are bitwise deterministic, and with team == 1
+ * bitwise equal to ljmd_compute_forces on the tiled list the CSR came from.
+ *   team     1, 2, 4, 8 or 16
+ *   offsets, csr  as produced by ljmd_list_to_csr (entries must be in [0, n))
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_FORCES_CSR, n, 0, ntypes) when
+ *            ev or e_atom is given
+ * Other arguments as in ljmd_compute_forces.
+ */
+int ljmd_compute_forces_csr(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                            const double *eps_packed, const double *sigma_packed, int64_t n,
+                            const double *x, const int32_t *type, const int64_t *offsets,
+                            const int32_t *csr, int32_t team, double *F, double *e_atom,
+                            double *ev, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- elementwise steps of the discrete velocity-Verlet adjoint ----
  *

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libljmd.so")
-SOURCES = ["api.hip", "bin.hip", "neighbor.hip", "force.hip", "backward.hip", "integrate.hip"]
+SOURCES = ["api.hip", "bin.hip", "neighbor.hip", "force.hip", "backward.hip", "integrate.hip",
+           "csr.hip"]
 ARCH = os.environ.get("LJMD_OFFLOAD_ARCH", "gfx950")
 
 

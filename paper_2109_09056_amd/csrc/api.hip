@@ -32,6 +32,14 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
                     const int32_t *nbr, const int32_t *nnbr, int32_t maxn, const double *g,
                     double *gx, double *geps, double *gsig, int accumulate, void *ws,
                     hipStream_t st);
+size_t csr_workspace(int64_t n);
+int launch_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                       int64_t *offsets, int32_t *csr, int64_t cap, void *ws, hipStream_t st);
+size_t csr_force_workspace(int64_t n);
+int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                      const double *sig, int64_t n, const double *x, const int32_t *type,
+                      const int64_t *offsets, const int32_t *csr, int team, double *F,
+                      double *e_atom, double *ev, void *ws, hipStream_t st);
 size_t stream_workspace(int64_t n);
 int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n, double *x,
                      double *v, const double *F, double *ke, void *ws, hipStream_t st);
@@ -170,6 +178,8 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
       return bwd_workspace(n, ntypes < 1 ? 1 : (ntypes > LJMD_MAX_TYPES ? LJMD_MAX_TYPES : ntypes));
     case LJMD_OP_INTEGRATE:
     case LJMD_OP_LOSS: return stream_workspace(n);
+    case LJMD_OP_CSR: return csr_workspace(n);
+    case LJMD_OP_FORCES_CSR: return csr_force_workspace(n);
     default: return 0;
   }
 }
@@ -233,6 +243,40 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
   LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? force_workspace(n) : 0));
   return launch_forces(make_box(box), precision, kind, rc, ntypes, eps_packed, sigma_packed, n, x,
                        type, nbr, nnbr, maxn, F, e_atom, ev, ws, (hipStream_t)stream);
+}
+
+int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                     int64_t *offsets, int32_t *csr, int64_t cap, void *ws, size_t ws_bytes,
+                     void *stream) {
+  LJMD_TRY(check_n(n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (cap < 0) return set_error(LJMD_EINVAL, "cap = %lld must be >= 0", (long long)cap);
+  if (!offsets) return set_error(LJMD_EINVAL, "offsets is NULL");
+  if (n > 0 && (!nbr || !nnbr)) return set_error(LJMD_EINVAL, "nbr/nnbr is NULL");
+  if (cap > 0 && !csr) return set_error(LJMD_EINVAL, "csr is NULL with cap > 0");
+  LJMD_TRY(check_ws(ws, ws_bytes, csr_workspace(n)));
+  return launch_list_to_csr(n, nbr, nnbr, maxn, offsets, csr, cap, ws, (hipStream_t)stream);
+}
+
+int ljmd_compute_forces_csr(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                            const double *eps_packed, const double *sigma_packed, int64_t n,
+                            const double *x, const int32_t *type, const int64_t *offsets,
+                            const int32_t *csr, int32_t team, double *F, double *e_atom,
+                            double *ev, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  if (team != 1 && team != 2 && team != 4 && team != 8 && team != 16)
+    return set_error(LJMD_EINVAL, "team = %d must be 1, 2, 4, 8 or 16", team);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (n > 0 && (!x || !offsets || !csr || !F))
+    return set_error(LJMD_EINVAL, "x/offsets/csr/F is NULL");
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? csr_force_workspace(n) : 0));
+  return launch_forces_csr(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x,
+                           type, offsets, csr, team, F, e_atom, ev, ws, (hipStream_t)stream);
 }
 
 int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64_t n,

@@ -21,6 +21,8 @@
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
 // column-sum launch (deterministic).
+#include <type_traits>
+
 #include "common.h"
 
 namespace ljmd {
@@ -377,6 +379,127 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
   }
 }
 
+// CSR list, `TEAM` lanes per atom (hierarchical traversal): lane t of an
+// atom's team takes the row entries t, t + TEAM, ... in groups of U (whole
+// groups first, the partial group gathers only live slots), then the team's
+// sums are combined by a butterfly over the team (both lanes of every exchange
+// add the same two numbers, so every lane ends with the same, order-fixed sum).
+// TEAM = 1 walks the row in order: the same sums as k_force_full.
+template <bool MIXED, bool T1, bool EV, int TEAM, int U, bool WIDE>
+__global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
+                                                            const int64_t *__restrict__ off,
+                                                            const int32_t *__restrict__ csr) {
+  __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
+  __shared__ double red[kForceWaves * 8];
+  Coef c1{};
+  if constexpr (T1) {
+    c1 = coef_of(a.eps, a.sig, 0);
+  } else {
+    load_table(a, tab);
+  }
+  constexpr int kAtoms = kForceThreads / TEAM;  // atoms per block
+  const int t = threadIdx.x % TEAM;
+  const int64_t i64 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAtoms + threadIdx.x / TEAM;
+  const bool live = i64 < a.n;
+  const int32_t i = live ? (int32_t)i64 : 0;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = a.x[3 * (int64_t)i];
+    yi = a.x[3 * (int64_t)i + 1];
+    zi = a.x[3 * (int64_t)i + 2];
+  }
+  const double m = a.rc;
+  const bool in = !live || (xi >= m && xi <= a.b.L[0] - m && yi >= m && yi <= a.b.L[1] - m &&
+                            zi >= m && zi <= a.b.L[2] - m);
+  const bool interior = __ballot(!in) == 0;  // wavefront-uniform
+  Acc s;
+  if (live) {
+    const int ti = T1 ? 0 : a.type[i];
+    const int64_t r0 = off[i], r1 = off[i + 1];
+    const int32_t cnt = r1 - r0 > t ? (int32_t)((r1 - r0 - t + TEAM - 1) / TEAM) : 0;
+    const int32_t *row = csr + r0 + t;
+    auto walk = [&](auto wrap) {
+      constexpr bool W = decltype(wrap)::value;
+      const int32_t whole = cnt - cnt % U;
+      const int32_t *rp = row;
+      int32_t k = 0;
+      for (; k < whole; k += U, rp += U * TEAM) {
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = rp[u * TEAM];
+        double xj[U], yj[U], zj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double *p = pos_of<WIDE>(a.x, j[u]);
+          xj[u] = p[0];
+          yj[u] = p[1];
+          zj[u] = p[2];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          add_pair<MIXED, T1, EV, W>(a, xi, yi, zi, xj[u], yj[u], zj[u], j[u], true, ti, c1, tab, s);
+      }
+      if (k < cnt) {
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = rp[(k + u < cnt ? u : 0) * TEAM];
+        double xj[U], yj[U], zj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          xj[u] = xi;
+          yj[u] = yi;
+          zj[u] = zi;
+          if (k + u < cnt) {
+            const double *p = pos_of<WIDE>(a.x, j[u]);
+            xj[u] = p[0];
+            yj[u] = p[1];
+            zj[u] = p[2];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          add_pair<MIXED, T1, EV, W>(a, xi, yi, zi, xj[u], yj[u], zj[u], j[u], k + u < cnt, ti, c1,
+                                     tab, s);
+      }
+    };
+    if (interior)
+      walk(std::false_type{});
+    else
+      walk(std::true_type{});
+  }
+  if constexpr (TEAM > 1) {
+#pragma unroll
+    for (int mask = TEAM / 2; mask > 0; mask >>= 1) {
+      s.fx += __shfl_xor(s.fx, mask, kWave);
+      s.fy += __shfl_xor(s.fy, mask, kWave);
+      s.fz += __shfl_xor(s.fz, mask, kWave);
+      if constexpr (EV) {
+        s.e += __shfl_xor(s.e, mask, kWave);
+        s.wxx += __shfl_xor(s.wxx, mask, kWave);
+        s.wyy += __shfl_xor(s.wyy, mask, kWave);
+        s.wzz += __shfl_xor(s.wzz, mask, kWave);
+        s.wxy += __shfl_xor(s.wxy, mask, kWave);
+        s.wxz += __shfl_xor(s.wxz, mask, kWave);
+        s.wyz += __shfl_xor(s.wyz, mask, kWave);
+      }
+    }
+  }
+  const bool lead = live && t == 0;
+  if (lead) {
+    a.F[3 * (int64_t)i] = s.fx;
+    a.F[3 * (int64_t)i + 1] = s.fy;
+    a.F[3 * (int64_t)i + 2] = s.fz;
+    if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
+  }
+  if constexpr (EV) {
+    const double z = 0.0;
+    const double v[7] = {lead ? 0.5 * s.e : z,   lead ? 0.5 * s.wxx : z, lead ? 0.5 * s.wyy : z,
+                         lead ? 0.5 * s.wzz : z, lead ? 0.5 * s.wxy : z, lead ? 0.5 * s.wxz : z,
+                         lead ? 0.5 * s.wyz : z};
+    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+  }
+}
+
 // Full-list loop shape: 8 slots per iteration with the exact interior fast
 // path (measured best on MI355X against 1, 2 and 4 slots, with and without it).
 constexpr int kUnroll = 8;
@@ -445,6 +568,82 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   }
   if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces");
+}
+
+// CSR forces: blocks of kForceThreads / team atoms.
+unsigned csr_force_blocks(int64_t n, int team) {
+  const int64_t apb = kForceThreads / team;
+  const int64_t b = (n + apb - 1) / apb;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+size_t csr_force_workspace(int64_t n) {
+  return (size_t)csr_force_blocks(n, LJMD_MAX_TEAM) * kEvStride * sizeof(double);
+}
+
+namespace {
+template <bool MIXED, bool T1, bool EV, int TEAM>
+void launch_csr_team(const ForceArgs &a, const int64_t *off, const int32_t *csr, hipStream_t st) {
+  constexpr int U = TEAM == 1 ? kUnroll : 4;
+  const unsigned nblk = csr_force_blocks(a.n, TEAM);
+  if (a.n <= kNarrowAtoms)
+    k_force_csr<MIXED, T1, EV, TEAM, U, false><<<nblk, kForceThreads, 0, st>>>(a, off, csr);
+  else
+    k_force_csr<MIXED, T1, EV, TEAM, U, true><<<nblk, kForceThreads, 0, st>>>(a, off, csr);
+}
+
+template <bool MIXED, bool T1, bool EV>
+void launch_csr_kind(const ForceArgs &a, int team, const int64_t *off, const int32_t *csr,
+                     hipStream_t st) {
+  switch (team) {
+    case 1: launch_csr_team<MIXED, T1, EV, 1>(a, off, csr, st); break;
+    case 2: launch_csr_team<MIXED, T1, EV, 2>(a, off, csr, st); break;
+    case 4: launch_csr_team<MIXED, T1, EV, 4>(a, off, csr, st); break;
+    case 8: launch_csr_team<MIXED, T1, EV, 8>(a, off, csr, st); break;
+    default: launch_csr_team<MIXED, T1, EV, 16>(a, off, csr, st); break;
+  }
+}
+
+template <bool MIXED>
+void launch_csr_prec(const ForceArgs &a, int team, bool ev, const int64_t *off,
+                     const int32_t *csr, hipStream_t st) {
+  const bool t1 = a.ntypes == 1;
+  if (t1 && ev) launch_csr_kind<MIXED, true, true>(a, team, off, csr, st);
+  else if (t1) launch_csr_kind<MIXED, true, false>(a, team, off, csr, st);
+  else if (ev) launch_csr_kind<MIXED, false, true>(a, team, off, csr, st);
+  else launch_csr_kind<MIXED, false, false>(a, team, off, csr, st);
+}
+}  // namespace
+
+int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                      const double *sig, int64_t n, const double *x, const int32_t *type,
+                      const int64_t *offsets, const int32_t *csr, int team, double *F,
+                      double *e_atom, double *ev, void *ws, hipStream_t st) {
+  ForceArgs a{};
+  a.b = b;
+  a.rc = rc;
+  a.rc2 = rc * rc;
+  a.ntypes = ntypes;
+  a.eps = eps;
+  a.sig = sig;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.type = type;
+  a.F = F;
+  a.e_atom = e_atom;
+  a.partial = (double *)ws;
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  const unsigned nblk = csr_force_blocks(n, team);
+  if (n > 0) {
+    if (precision == LJMD_MIXED)
+      launch_csr_prec<true>(a, team, want_ev, offsets, csr, st);
+    else
+      launch_csr_prec<false>(a, team, want_ev, offsets, csr, st);
+  } else if (ev) {
+    k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
+  }
+  if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
+  return check_launch("ljmd_compute_forces_csr");
 }
 
 int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,

@@ -15,8 +15,8 @@ import torch
 from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
-                   MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_FORCES, OP_INTEGRATE, OP_LOSS,
-                   TILE, LjmdError, make_box)
+                   MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
+                   OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, TILE, LjmdError, make_box)
 
 
 def _ptr(t):
@@ -147,6 +147,63 @@ def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn
         ctypes.byref(b), int(precision), int(kind), float(rc), ntypes, _ptr(eps), _ptr(sigma), n,
         _ptr(x), _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(F), _ptr(e_atom), _ptr(ev),
         _ptr(ws), need, _stream(dev)), "ljmd_compute_forces")
+    return F, e_atom, ev
+
+
+def list_to_csr(nbr, nnbr, maxn, cap=None, offsets=None, csr=None, ws=None):
+    """(offsets int64 [n+1], csr int32 [cap]) = compressed copy of a tiled list.  With
+    cap None the capacity is the exact total, read back from the device (a sync)."""
+    n = nnbr.shape[0]
+    dev = nnbr.device
+    _need(nnbr, "nnbr", torch.int32, (n,))
+    _need(nbr, "nbr", torch.int32, None, dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if cap is None:
+        cap = int(nnbr.clamp(max=maxn).to(torch.int64).sum().item())
+    if offsets is None:
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    if csr is None:
+        csr = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    _need(offsets, "offsets", torch.int64, (n + 1,), dev)
+    _need(csr, "csr", torch.int32, None, dev)
+    if csr.numel() < cap:
+        raise ValueError("csr is smaller than cap")
+    ws, need = _ws(OP_CSR, n, dev, ws=ws)
+    _lib.check(_lib.load().ljmd_list_to_csr(n, _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(offsets),
+                                            _ptr(csr), int(cap), _ptr(ws), need, _stream(dev)),
+               "ljmd_list_to_csr")
+    return offsets, csr
+
+
+def compute_forces_csr(L, precision, rc, eps, sigma, x, types, offsets, csr, team=1, F=None,
+                       e_atom=None, ev=None, want_energy=True, ws=None):
+    """Forces over a CSR list with `team` lanes per atom (FULL rows)."""
+    n = x.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (n, 3))
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(offsets, "offsets", torch.int64, (n + 1,), dev)
+    _need(csr, "csr", torch.int32, None, dev)
+    if F is None:
+        F = torch.empty_like(x)
+    if want_energy:
+        if e_atom is None:
+            e_atom = torch.empty(n, dtype=torch.float64, device=dev)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_atom, "e_atom", torch.float64, (n,), dev)
+    _need(ev, "ev", torch.float64, (7,), dev)
+    ws, need = _ws(OP_FORCES_CSR, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_compute_forces_csr(
+        ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, _ptr(x),
+        _ptr(types), _ptr(offsets), _ptr(csr), int(team), _ptr(F), _ptr(e_atom), _ptr(ev),
+        _ptr(ws), need, _stream(dev)), "ljmd_compute_forces_csr")
     return F, e_atom, ev
 
 

@@ -102,6 +102,24 @@ def test_validation_rejects_bad_arguments(lib):
     # energy requested without workspace
     assert call(lib, "ljmd_compute_forces", bb, 0, 0, 2.5, 1, fake, fake, 10, fake, None, fake,
                 fake, 8, fake, fake, fake, None, 0, None) == lib.EWORKSPACE
+    # CSR: bad maxn, negative cap, missing offsets, csr missing with cap > 0, no workspace
+    assert call(lib, "ljmd_list_to_csr", 10, fake, fake, 0, fake, fake, 100, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_list_to_csr", 10, fake, fake, 8, fake, fake, -1, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_list_to_csr", 10, fake, fake, 8, None, fake, 100, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_list_to_csr", 10, fake, fake, 8, fake, None, 100, fake, 1 << 20,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_list_to_csr", 10, fake, fake, 8, fake, fake, 100, None, 0,
+                None) == lib.EWORKSPACE
+    # CSR forces: team outside {1, 2, 4, 8, 16}, bad precision, energy without workspace
+    cargs = lambda prec, team, ev: (bb, prec, 2.5, 1, fake, fake, 10, fake, None, fake, fake,
+                                    team, fake, None, ev, None, 0, None)
+    for team in (0, 3, 32, -4):
+        assert call(lib, "ljmd_compute_forces_csr", *cargs(0, team, None)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces_csr", *cargs(4, 1, None)) == lib.EINVAL
+    assert call(lib, "ljmd_compute_forces_csr", *cargs(0, 4, fake)) == lib.EWORKSPACE
     # integrate: bad stage, zero dt, bad mass
     assert call(lib, "ljmd_integrate", 7, 0.005, 1.0, bb, 10, fake, fake, fake, None, None, 0,
                 None) == lib.EINVAL

@@ -1,0 +1,139 @@
+"""Compressed (CSR) neighbor lists and team-per-atom force traversal: rows equal to the
+tiled list they come from, forces and energies against the oracle for every team size,
+team 1 bitwise equal to the tiled lane-per-atom kernel, every team deterministic."""
+import numpy as np
+import pytest
+
+import lj_inputs as li
+from helpers import decode_rows, gpu_device, max_rel_vec
+
+pytestmark = pytest.mark.gpu
+
+TEAMS = (1, 2, 4, 8, 16)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def _case(name):
+    """(box, caller-order positions, types, eps, sigma) of a named input."""
+    if name == "gas1000":  # ragged n, uniform random, one type
+        rng = np.random.default_rng(11)
+        L = np.array([12.0, 13.0, 14.0])
+        return L, rng.uniform(0, 1, (1000, 3)) * L, np.zeros(1000, np.int32), [1.0], [1.0]
+    w = li.WORKLOADS[name]
+    if w.ntypes == 1:
+        return w.box, li.positions(w), np.zeros(w.natoms, np.int32), [1.0], [1.0]
+    eps, sig = li.params(w)
+    return w.box, li.positions(w), li.types(w), eps, sig
+
+
+_ORACLE = {}
+
+
+def _oracle(orc, name):
+    if name not in _ORACLE:
+        L, x, ty, eps, sig = _case(name)
+        _ORACLE[name] = orc.forces(x, L, 2.5, eps, sig, ty if len(eps) > 1 else None)
+    return _ORACLE[name]
+
+
+def _sim(dev, name):
+    from paper_2109_09056_amd import md, ops
+    L, x, ty, eps, sig = _case(name)
+    sim = md.LJSim(L, eps=eps, sigma=sig, precision=ops.FP64, kind=ops.FULL, device=dev)
+    sim.load(x, None, ty)
+    return sim
+
+
+@pytest.mark.parametrize("name", ["lj256", "gas1000", "lj32k", "lj32k_fm"])
+def test_csr_rows_equal_tiled(dev, name):
+    import torch
+    from paper_2109_09056_amd import ops
+    sim = _sim(dev, name)
+    nl = sim.nl
+    off, csr = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn)
+    rows = decode_rows(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn)
+    off_h, csr_h = off.cpu().numpy(), csr.cpu().numpy()
+    cnt = np.array([r.size for r in rows])
+    assert off_h[0] == 0 and np.array_equal(np.diff(off_h), cnt)
+    for i, r in enumerate(rows):
+        assert np.array_equal(csr_h[off_h[i]:off_h[i + 1]], r), i  # same order
+    # a capacity below the total: offsets unchanged, nothing written at or past cap
+    total = int(off_h[-1])
+    cap = total - 37
+    sentinel = torch.full((total + 16,), -7, dtype=torch.int32, device=dev)
+    off2, _ = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn, cap=cap, csr=sentinel)
+    s = sentinel.cpu().numpy()
+    assert np.array_equal(off2.cpu().numpy(), off_h)
+    assert np.array_equal(s[:cap], csr_h[:cap]) and np.all(s[cap:] == -7)
+
+
+def test_csr_empty(dev):
+    import torch
+    from paper_2109_09056_amd import ops
+    nbr = torch.zeros(64 * 8, dtype=torch.int32, device=dev)
+    nnbr = torch.zeros(0, dtype=torch.int32, device=dev)
+    off, _ = ops.list_to_csr(nbr, nnbr, 8, cap=0)
+    assert off.cpu().tolist() == [0]
+    x = torch.zeros((0, 3), dtype=torch.float64, device=dev)
+    one = torch.ones(1, dtype=torch.float64, device=dev)
+    _, _, ev = ops.compute_forces_csr([10.0, 10.0, 10.0], ops.FP64, 2.5, one, one, x,
+                                      torch.zeros(0, dtype=torch.int32, device=dev), off,
+                                      torch.zeros(1, dtype=torch.int32, device=dev), team=4)
+    assert torch.count_nonzero(ev).item() == 0
+
+
+@pytest.mark.parametrize("name", ["lj256", "gas1000", "lj32k", "lj32k_fm"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_csr_forces_vs_oracle(dev, orc, name, prec):
+    """Every team size against the oracle (FP64 1e-12; mixed 1e-5 F_rms, 1e-6 per-atom e)."""
+    from paper_2109_09056_amd import ops
+    Fo, eo, Wo, _ = _oracle(orc, name)
+    sim = _sim(dev, name)
+    nl = sim.nl
+    off, csr = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn)
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    for team in TEAMS:
+        F, e, ev = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types,
+                                          off, csr, team=team)
+        Fg = sim.in_caller_order(F).cpu().numpy()
+        eg = sim.in_caller_order(e).cpu().numpy()
+        ev = ev.cpu().numpy()
+        if P == ops.FP64:
+            assert max_rel_vec(Fg, Fo) <= 1e-12, team
+            assert np.abs(eg - eo).max() <= 1e-12 * np.abs(eo).max(), team
+            assert ev[0] == pytest.approx(eo.sum(), rel=1e-12)
+            assert np.abs(ev[1:] - Wo).max() <= 1e-12 * np.abs(Wo[:3]).max()
+        else:
+            frms = np.sqrt((Fo * Fo).sum() / Fo.shape[0])
+            assert np.linalg.norm(Fg - Fo, axis=1).max() <= 1e-5 * frms, team
+            assert (np.abs(eg - eo) / np.maximum(np.abs(eo), 1e-3)).max() <= 1e-6, team
+            assert ev[0] == pytest.approx(eo.sum(), rel=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_csr_team1_bitwise_tiled_and_teams_deterministic(dev, prec):
+    import torch
+    from paper_2109_09056_amd import ops
+    sim = _sim(dev, "lj32k_fm")
+    nl = sim.nl
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    off, csr = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn)
+    Ft, et, evt = ops.compute_forces(sim.L, P, ops.FULL, 2.5, sim.eps, sim.sigma, sim.x,
+                                     sim.types, nl.nbr, nl.nnbr, nl.maxn)
+    F1, e1, ev1 = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types,
+                                         off, csr, team=1)
+    assert torch.equal(F1, Ft) and torch.equal(e1, et) and torch.equal(ev1, evt)
+    for team in TEAMS:
+        a = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types, off, csr,
+                                   team=team)
+        b = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types, off, csr,
+                                   team=team)
+        assert all(torch.equal(u, v) for u, v in zip(a, b)), team
+        # forces only (no energy): the same forces
+        Fn, _, _ = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types,
+                                          off, csr, team=team, want_energy=False)
+        assert torch.equal(Fn, a[0]), team
