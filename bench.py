@@ -208,6 +208,32 @@ def rebuild_time(sim, reps=20):
     return round((time.perf_counter() - t0) / reps * 1e6, 2)
 
 
+def traversal_study(w, sim, reps=50):
+    """Forces + energy/virial of the 500k workload (mixed) over the same pairs: the dense
+    tiled list with one lane per atom (the production kernel) against its CSR copy with
+    1, 2, 4, 8 and 16 lanes per atom; plus the tiled -> CSR conversion."""
+    import torch
+    from paper_2109_09056_amd import ops
+    nl = sim.nl
+    off, csr = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn)
+    cap = csr.numel()
+    wsc = torch.empty(ops.workspace_bytes(ops.OP_CSR, sim.n), dtype=torch.uint8, device=sim.device)
+    wsf = torch.empty(ops.workspace_bytes(ops.OP_FORCES_CSR, sim.n), dtype=torch.uint8,
+                      device=sim.device)
+    F, e = torch.empty_like(sim.F), torch.empty_like(sim.e_atom)
+    ev = torch.empty(7, dtype=torch.float64, device=sim.device)
+    out = {"list_to_csr_us": round(event_time(lambda: ops.list_to_csr(
+        nl.nbr, nl.nnbr, nl.maxn, cap=cap, offsets=off, csr=csr, ws=wsc), reps) * 1e3, 2)}
+    out["tiled_lane_per_atom_us"] = round(event_time(lambda: ops.compute_forces(
+        w.box, ops.MIXED, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
+        nl.nnbr, nl.maxn, F=F, e_atom=e, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+    for team in (1, 2, 4, 8, 16):
+        out[f"csr_team{team}_us"] = round(event_time(lambda: ops.compute_forces_csr(
+            w.box, ops.MIXED, w.rc, sim.eps, sim.sigma, sim.x, sim.types, off, csr, team=team,
+            F=F, e_atom=e, ev=ev, ws=wsf), reps) * 1e3, 2)
+    return out
+
+
 def shard_share(dev, steps=200, warmup=40):
     """One GPU's share of the 500,000-atom box split 2x2x2 over eight GPUs: the owned
     brick (edge L/2) plus its ghost shell of thickness rlist, cut from the same input
@@ -316,6 +342,8 @@ def main():
                         "mixed_over_fp64": round(t64 / t_mixed, 4)}
         log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
         line["fp64"]["mixed_error_vs_fp64"] = mixed_error(w, sim)
+        line["traversal_study"] = traversal_study(w, sim)
+        log(f"[bench] traversal study: {line['traversal_study']}")
         line["rebuild_us"] = rebuild_time(sim)
         line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),
                            "trajectory_256k": bwd_fwd_trajectory(dev)}
