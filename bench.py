@@ -26,14 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Counter figures of the fused step kernel k_force_full<mixed, one type, EV, 8, interior,
-# step, narrow> on the 500,000-atom workload, from the rocprofv3 summaries committed in
+# Counter figures of the fused step kernel k_force_full<mixed, one type, EV, 6, interior,
+# step, narrow, team 2> on the 500,000-atom workload, from the rocprofv3 summaries committed in
 # profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
 # HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
 # gives the two counters); set to None whenever the kernel changes until re-measured.
-FORCE_TRAFFIC = 231.14e6
-FORCE_VALU_BUSY = 0.510
-FORCE_TA_BUSY = 0.750
+FORCE_TRAFFIC = 235.27e6
+FORCE_VALU_BUSY = 0.554
+FORCE_TA_BUSY = 0.728
 
 
 def log(msg):
@@ -210,8 +210,8 @@ def rebuild_time(sim, reps=20):
 
 def traversal_study(w, sim, reps=50):
     """Forces + energy/virial of the 500k workload (mixed) over the same pairs: the dense
-    tiled list with one lane per atom (the production kernel) against its CSR copy with
-    1, 2, 4, 8 and 16 lanes per atom; plus the tiled -> CSR conversion."""
+    tiled list walked by two lanes per atom (the production kernel) against its CSR copy
+    walked by 1, 2, 4, 8 and 16 lanes per atom; plus the tiled -> CSR conversion."""
     import torch
     from paper_2109_09056_amd import ops
     nl = sim.nl
@@ -224,7 +224,7 @@ def traversal_study(w, sim, reps=50):
     ev = torch.empty(7, dtype=torch.float64, device=sim.device)
     out = {"list_to_csr_us": round(event_time(lambda: ops.list_to_csr(
         nl.nbr, nl.nnbr, nl.maxn, cap=cap, offsets=off, csr=csr, ws=wsc), reps) * 1e3, 2)}
-    out["tiled_lane_per_atom_us"] = round(event_time(lambda: ops.compute_forces(
+    out["tiled_team2_us"] = round(event_time(lambda: ops.compute_forces(
         w.box, ops.MIXED, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
         nl.nnbr, nl.maxn, F=F, e_atom=e, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
     for team in (1, 2, 4, 8, 16):
@@ -326,7 +326,7 @@ def main():
                    "natoms": n, "precision": "mixed", "list": "full",
                    "mean_list_length": round(nbar, 3), "maxn": sim.nl.maxn},
         "roofline": {"bound": "hbm",
-                     "kernel": "k_force_full<mixed, step> fused force+integration "
+                     "kernel": "k_force_full<mixed, step, team 2> fused force+integration "
                                "(+ energy/virial/KE column sum)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

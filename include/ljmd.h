@@ -272,8 +272,9 @@ int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t
  * (paper: Cabana's hierarchical neighbor traversal -- one thread per particle
  * or a team of threads per particle; "Parallel Loops").  Lane t of a team takes
  * row entries t, t + team, ...; the team's sums are combined in a fixed
- * butterfly order, so results are bitwise deterministic, and with team == 1
- * bitwise equal to ljmd_compute_forces on the tiled list the CSR came from.
+ * butterfly order, so results are bitwise deterministic.  ljmd_compute_forces
+ * walks a FULL tiled list with teams of two, and with team == 2 the forces and
+ * per-atom energies here are bitwise those (E and W agree to rounding).
  *   team     1, 2, 4, 8 or 16
  *   offsets, csr  as produced by ljmd_list_to_csr (entries must be in [0, n))
  *   ws       >= ljmd_workspace_bytes(LJMD_OP_FORCES_CSR, n, 0, ntypes) when

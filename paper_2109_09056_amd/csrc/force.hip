@@ -14,9 +14,9 @@
 // accumulation of F, e, E and W are FP64.  The pair energy u is taken in
 // FP64 from the FP32 reciprocal refined by one FP64 Newton step.
 //
-// FULL list: lane i of the grid owns atom i and walks its row of the tile
-// (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l], one coalesced
-// 256-byte load per wavefront per k); no atomics, fixed summation order, so
+// FULL list: a team of two lanes owns atom i and walks its row of the tile
+// (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l]; the team's lanes
+// take the even and the odd entries); no atomics, fixed summation order, so
 // the result is bitwise reproducible.  HALF list: the owner adds s*d to F_i in
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
@@ -174,21 +174,23 @@ __device__ __forceinline__ void add_pair(const ForceArgs &a, double xi, double y
 // row pointer (no per-slot address arithmetic); the last, partial group loads
 // indices and positions only for slots below cnt.
 // Slots are visited in row order, so the sums are the same as one slot at a
-// time.  WRAP = false skips the minimum image; the caller only takes that
+// time.  STRIDE > 1: the lane owns every STRIDE-th entry of the row (row points
+// at its first one).  WRAP = false skips the minimum image; the caller only takes that
 // path when every atom of the wavefront is at least rc from all box faces,
 // where any pair closer than rc has the same raw and minimum-image
 // displacement, and any other pair has some |raw component| above L/2 > rc
 // and is rejected by the cutoff test either way.
-template <bool MIXED, bool T1, bool EV, int U, bool WRAP, bool WIDE>
+template <bool MIXED, bool T1, bool EV, int U, bool WRAP, bool WIDE, int STRIDE = 1>
 __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row, int32_t cnt,
                                          double xi, double yi, double zi, int ti,
                                          const Coef &c1, const double *tab, Acc &s) {
+  constexpr int kStep = STRIDE * kWave;  // ints between this lane's consecutive entries
   const int32_t whole = cnt - cnt % U;
   int32_t k = 0;
-  for (; k < whole; k += U, row += U * kWave) {
+  for (; k < whole; k += U, row += U * kStep) {
     int32_t j[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) j[u] = row[u * kWave];
+    for (int u = 0; u < U; ++u) j[u] = row[u * kStep];
     double xj[U], yj[U], zj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -205,7 +207,7 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
   if (k < cnt) {
     int32_t j[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) j[u] = row[(k + u < cnt ? u : 0) * kWave];
+    for (int u = 0; u < U; ++u) j[u] = row[(k + u < cnt ? u : 0) * kStep];
     double xj[U], yj[U], zj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -226,22 +228,32 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
   }
 }
 
-// STEP: after the row, the lane also finishes its atom's velocity-Verlet step
-// -- closing half kick (kinetic energy taken there), and when open_next the
-// next step's half kick, drift and wrap into x_next -- with exactly the
+// TEAM lanes per atom: lane t of an atom's team walks the row entries t,
+// t + TEAM, ...; neighbouring entries of one row are mostly nearby atoms, so
+// the lanes of a team gather from nearby addresses and each gather instruction
+// touches fewer cache lines than with one lane per atom.  The team's force
+// and per-atom energy are combined by a butterfly over the team (both lanes
+// of every exchange add the same two numbers: every lane ends with the same,
+// order-fixed sum); energy and virial partials enter the block sum per lane.
+//
+// STEP: after the row, the team also finishes its atom's velocity-Verlet
+// step -- closing half kick (kinetic energy taken there), and when open_next
+// the next step's half kick, drift and wrap into x_next -- with exactly the
 // operations of ljmd_integrate, so the trajectory is bitwise the same as the
-// unfused calls.  Partial rows then carry the kinetic energy in column 7.
-template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE>
-__global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
+// unfused calls; lane t handles components t, t + TEAM, ...  Partial rows
+// then carry the kinetic energy in column 7.
+template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE, int TEAM>
+__global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
-  __shared__ double red[kForceWaves * 8];
+  __shared__ double red[kForceWaves * TEAM * 8];
   Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
   } else {
     load_table(a, tab);
   }
-  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + threadIdx.x;
+  const int t = (int)threadIdx.x % TEAM;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + (int)threadIdx.x / TEAM;
   Acc s;
   double ke = 0.0;
   const bool live = i < a.n;
@@ -260,23 +272,40 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
   }
   if (live) {
     const int ti = T1 ? 0 : a.type[i];
-    const int32_t cnt = a.nnbr[i];
-    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
+    const int32_t ctot = a.nnbr[i];
+    const int32_t cnt = ctot > t ? (ctot - t + TEAM - 1) / TEAM : 0;
+    const int32_t *row =
+        a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
     if (SKIP && interior)
-      walk_row<MIXED, T1, EV, U, false, WIDE>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+      walk_row<MIXED, T1, EV, U, false, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     else
-      walk_row<MIXED, T1, EV, U, true, WIDE>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
-    if (!STEP || a.F) {
-      a.F[3 * (int64_t)i] = s.fx;
-      a.F[3 * (int64_t)i + 1] = s.fy;
-      a.F[3 * (int64_t)i + 2] = s.fz;
+      walk_row<MIXED, T1, EV, U, true, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+  }
+  const double e_lane = s.e;
+  if constexpr (TEAM > 1) {
+#pragma unroll
+    for (int mask = TEAM / 2; mask > 0; mask >>= 1) {
+      s.fx += __shfl_xor(s.fx, mask, kWave);
+      s.fy += __shfl_xor(s.fy, mask, kWave);
+      s.fz += __shfl_xor(s.fz, mask, kWave);
+      if constexpr (EV) s.e += __shfl_xor(s.e, mask, kWave);
     }
-    if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
+  }
+  if (live) {
+    if (t == 0) {
+      if (!STEP || a.F) {
+        a.F[3 * (int64_t)i] = s.fx;
+        a.F[3 * (int64_t)i + 1] = s.fy;
+        a.F[3 * (int64_t)i + 2] = s.fz;
+      }
+      if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
+    }
     if constexpr (STEP) {
       const double f[3] = {s.fx, s.fy, s.fz};
       const double xo[3] = {xi, yi, zi};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
+        if (k % TEAM != t) continue;
         const int64_t q = 3 * (int64_t)i + k;
         double kick = a.hdt * f[k];
         if (!a.unit_mass) kick = kick / a.mass;
@@ -298,9 +327,9 @@ __global__ __launch_bounds__(kForceThreads) void k_force_full(ForceArgs a) {
     }
   }
   if constexpr (EV) {
-    const double v[8] = {0.5 * s.e,   0.5 * s.wxx, 0.5 * s.wyy, 0.5 * s.wzz,
-                         0.5 * s.wxy, 0.5 * s.wxz, 0.5 * s.wyz, 0.5 * a.mass * ke};
-    block_sum<kForceWaves, 8>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+    const double v[8] = {0.5 * e_lane, 0.5 * s.wxx, 0.5 * s.wyy, 0.5 * s.wzz,
+                         0.5 * s.wxy,  0.5 * s.wxz, 0.5 * s.wyz, 0.5 * a.mass * ke};
+    block_sum<kForceWaves * TEAM, 8>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
   }
 }
 
@@ -384,7 +413,9 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
 // groups first, the partial group gathers only live slots), then the team's
 // sums are combined by a butterfly over the team (both lanes of every exchange
 // add the same two numbers, so every lane ends with the same, order-fixed sum).
-// TEAM = 1 walks the row in order: the same sums as k_force_full.
+// Each lane walks its entries in row order, as k_force_full does: with the
+// same team size the two kernels give bitwise the same forces and per-atom
+// energies.
 template <bool MIXED, bool T1, bool EV, int TEAM, int U, bool WIDE>
 __global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
                                                             const int64_t *__restrict__ off,
@@ -500,18 +531,25 @@ __global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
   }
 }
 
-// Full-list loop shape: 8 slots per iteration with the exact interior fast
-// path (measured best on MI355X against 1, 2 and 4 slots, with and without it).
+// Loop shapes, measured on MI355X.  One lane per atom (the CSR kernel with
+// team 1): 8 slots per group, against 1, 2 and 4.  Tiled full list: two lanes
+// per atom with 6 slots per group each, against one lane with 8 slots and
+// teams of 4 (fewer cache lines per gather instruction, with the
+// energy/virial partials still summed over 256 atoms per block).
 constexpr int kUnroll = 8;
+constexpr int kTeam = 2;
+constexpr int kTeamUnroll = 6;
 
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
   if (kind == LJMD_HALF)
     k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
   else if (a.n <= kNarrowAtoms)
-    k_force_full<MIXED, T1, EV, kUnroll, true, false, false><<<nblk, kForceThreads, 0, st>>>(a);
+    k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, false, kTeam>
+        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
   else
-    k_force_full<MIXED, T1, EV, kUnroll, true, false, true><<<nblk, kForceThreads, 0, st>>>(a);
+    k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, true, kTeam>
+        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
 }
 
 template <bool MIXED>
@@ -677,12 +715,14 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
   const unsigned nblk = force_blocks(n);
   const bool mixed = precision == LJMD_MIXED;
   const bool t1 = ntypes == 1;
-#define LJMD_STEP(M, T)                                                                     \
-  do {                                                                                      \
-    if (n <= kNarrowAtoms)                                                                  \
-      k_force_full<M, T, true, kUnroll, true, true, false><<<nblk, kForceThreads, 0, st>>>(a); \
-    else                                                                                    \
-      k_force_full<M, T, true, kUnroll, true, true, true><<<nblk, kForceThreads, 0, st>>>(a);  \
+#define LJMD_STEP(M, T)                                                                    \
+  do {                                                                                     \
+    if (n <= kNarrowAtoms)                                                                 \
+      k_force_full<M, T, true, kTeamUnroll, true, true, false, kTeam>                      \
+          <<<nblk, kForceThreads * kTeam, 0, st>>>(a);                                     \
+    else                                                                                   \
+      k_force_full<M, T, true, kTeamUnroll, true, true, true, kTeam>                       \
+          <<<nblk, kForceThreads * kTeam, 0, st>>>(a);                                     \
   } while (0)
   if (n > 0) {
     if (mixed) {
