@@ -22,8 +22,9 @@ namespace ljmd {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // atoms per block
 constexpr int kWaves = kThreads / kWave;
+constexpr int kTeam = 2;       // lanes per atom for one or two types
 
 struct BwdArgs {
   BoxK b;
@@ -84,17 +85,24 @@ __device__ __forceinline__ PairB pair_b(double r2, const BCoef &c) {
 }
 
 // TT: 1 or 2 types with register accumulators; 0: any T <= LJMD_MAX_TYPES with
-// lane-private LDS columns.
-template <bool MIXED, int TT, bool WIDE>
-__global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
+// lane-private LDS columns.  TEAM lanes per atom (TEAM > 1 only with TT > 0):
+// lane t of the team walks the row entries t, t + TEAM, ... (neighbouring
+// entries are mostly nearby atoms, so a gather instruction touches fewer
+// cache lines); gx is combined by a butterfly over the team (every lane ends
+// with the same, order-fixed sum) and the parameter-gradient partials enter
+// the block sums per lane.  A block always covers kThreads atoms.
+template <bool MIXED, int TT, bool WIDE, int TEAM>
+__global__ __launch_bounds__(kThreads * TEAM) void k_vjp(BwdArgs a) {
+  static_assert(TEAM == 1 || TT != 0, "lane-private LDS columns are sized for one lane per atom");
   constexpr int MT = LJMD_MAX_TYPES;
+  constexpr int NW = kWaves * TEAM;  // wavefronts per block
   __shared__ double tab[(TT == 1 ? 1 : MT * MT) * 7];
-  __shared__ double red[kWaves * (TT == 0 ? 1 : 2 * TT * TT)];
+  __shared__ double red[NW * (TT == 0 ? 1 : 2 * TT * TT)];
   __shared__ double acc[TT == 0 ? kThreads * 2 * MT : 1];
   __shared__ int32_t tid_type[TT == 0 ? kThreads : 1];
   const int T = TT == 0 ? a.ntypes : TT;
   if constexpr (TT != 1) {
-    for (int q = threadIdx.x; q < T * T; q += kThreads) {
+    for (int q = threadIdx.x; q < T * T; q += kThreads * TEAM) {
       const BCoef c = bcoef(a.eps, a.sig, packed_index(q / T, q % T, T));
       double *t = tab + 7 * q;
       t[0] = c.sig2; t[1] = c.c12; t[2] = c.c6; t[3] = c.d12; t[4] = c.d6; t[5] = c.q12; t[6] = c.q6;
@@ -107,7 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
   BCoef c1{};
   if constexpr (TT == 1) c1 = bcoef(a.eps, a.sig, 0);
 
-  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  const int tm = (int)threadIdx.x % TEAM;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + (int)threadIdx.x / TEAM;
   double ge[TT == 0 ? 1 : TT], gs[TT == 0 ? 1 : TT];
 #pragma unroll
   for (int q = 0; q < (TT == 0 ? 1 : TT); ++q) ge[q] = gs[q] = 0.0;
@@ -128,8 +137,10 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
     const double gxi = a.g[3 * (int64_t)i], gyi = a.g[3 * (int64_t)i + 1],
                  gzi = a.g[3 * (int64_t)i + 2];
     ti = TT == 1 ? 0 : a.type[i];
-    const int32_t cnt = a.nnbr[i];
-    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
+    const int32_t ctot = a.nnbr[i];
+    const int32_t cnt = ctot > tm ? (ctot - tm + TEAM - 1) / TEAM : 0;
+    const int32_t *row =
+        a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)tm * kWave;
     double ax = 0.0, ay = 0.0, az = 0.0;
     // one list entry: j with its position and cotangent
     auto entry = [&](auto wrap, int32_t j, const double *xj, const double *gj, bool valid) {
@@ -188,10 +199,11 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
       const int32_t whole = cnt - cnt % U;
       const int32_t *rp = row;
       int32_t k = 0;
-      for (; k < whole; k += U, rp += U * kWave) {
+      constexpr int kStep = TEAM * kWave;  // ints between this lane's consecutive entries
+      for (; k < whole; k += U, rp += U * kStep) {
         int32_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = rp[u * kWave];
+        for (int u = 0; u < U; ++u) jj[u] = rp[u * kStep];
         double xj[U][3], gj[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
       if (k < cnt) {
         int32_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = rp[(k + u < cnt ? u : 0) * kWave];
+        for (int u = 0; u < U; ++u) jj[u] = rp[(k + u < cnt ? u : 0) * kStep];
         double xj[U][3], gj[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -233,8 +245,18 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
       walk(std::false_type{});
     else
       walk(std::true_type{});
+    if constexpr (TEAM > 1) {
+#pragma unroll
+      for (int mask = TEAM / 2; mask > 0; mask >>= 1) {
+        ax += __shfl_xor(ax, mask, kWave);
+        ay += __shfl_xor(ay, mask, kWave);
+        az += __shfl_xor(az, mask, kWave);
+      }
+    }
     double *o = a.gx + 3 * (int64_t)i;
-    if (a.accumulate) {
+    if (tm != 0) {
+      // the team's lead lane writes gx
+    } else if (a.accumulate) {
       o[0] += ax;
       o[1] += ay;
       o[2] += az;
@@ -248,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
   double *out = a.partial + (int64_t)blockIdx.x * a.stride;
   if constexpr (TT == 1) {
     const double v[2] = {ge[0], gs[0]};
-    block_sum<kWaves, 2>(v, red, out);
+    block_sum<NW, 2>(v, red, out);
   } else if constexpr (TT == 2) {
     // layout: [which][a][b] -> which*4 + a*2 + b
     double v[8];
@@ -259,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(BwdArgs a) {
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
           v[w * 4 + aa * 2 + bb] = (ti == aa) ? (w == 0 ? ge[bb] : gs[bb]) : 0.0;
-    block_sum<kWaves, 8>(v, red, out);
+    block_sum<NW, 8>(v, red, out);
   } else {
     tid_type[threadIdx.x] = (i < a.n) ? ti : -1;
     __syncthreads();
@@ -338,19 +360,19 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
   const int stride = a.stride;
   double *colsums = a.partial + (size_t)nblk * stride;
   const bool mixed = precision == LJMD_MIXED;
-#define LJMD_VJP(M, TT)                                \
-  do {                                                 \
-    if (n <= kNarrowAtoms)                             \
-      k_vjp<M, TT, false><<<nblk, kThreads, 0, st>>>(a); \
-    else                                               \
-      k_vjp<M, TT, true><<<nblk, kThreads, 0, st>>>(a);  \
+#define LJMD_VJP(M, TT, TEAM)                                                \
+  do {                                                                       \
+    if (n <= kNarrowAtoms)                                                   \
+      k_vjp<M, TT, false, TEAM><<<nblk, kThreads * TEAM, 0, st>>>(a);       \
+    else                                                                     \
+      k_vjp<M, TT, true, TEAM><<<nblk, kThreads * TEAM, 0, st>>>(a);        \
   } while (0)
   if (ntypes == 1) {
-    if (mixed) LJMD_VJP(true, 1); else LJMD_VJP(false, 1);
+    if (mixed) LJMD_VJP(true, 1, kTeam); else LJMD_VJP(false, 1, kTeam);
   } else if (ntypes == 2) {
-    if (mixed) LJMD_VJP(true, 2); else LJMD_VJP(false, 2);
+    if (mixed) LJMD_VJP(true, 2, kTeam); else LJMD_VJP(false, 2, kTeam);
   } else {
-    if (mixed) LJMD_VJP(true, 0); else LJMD_VJP(false, 0);
+    if (mixed) LJMD_VJP(true, 0, 1); else LJMD_VJP(false, 0, 1);
   }
 #undef LJMD_VJP
   k_colsum<256><<<1, 256, 0, st>>>(nblk, stride, cols, a.partial, colsums, 1.0, 0);
