@@ -20,7 +20,8 @@
 // the result is bitwise reproducible.  HALF list: the owner adds s*d to F_i in
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
-// column-sum launch (deterministic).
+// column-sum launch (deterministic).  Full lists take the virial as
+// sum_i x_i (x) F_i plus the pairs that cross a box face (add_pair).
 #include <type_traits>
 
 #include "common.h"
@@ -133,15 +134,29 @@ struct Acc {
 
 // One neighbor j of atom i: minimum image (WRAP), cutoff test, pair force and
 // the row's accumulators.  `valid` is false for padding slots of a short group.
+//
+// Virial of the full list, W = 1/2 sum_i sum_j d_ij (x) f_ij with
+// d_ij = x_i - x_j + S_ij (S_ij = -k L, the minimum-image shift):
+//   W = sum_i x_i (x) F_i + 1/2 sum_i sum_j S_ij (x) f_ij,
+// exactly, component by component (sum_i f_ij = -F_j for the symmetric pair
+// set).  So a pair adds to W only when it crosses a box face (WRAP path,
+// S != 0), and every lane adds 2 x_i (x) (its part of F_i) once (add_xf).
 template <bool MIXED, bool T1, bool EV, bool WRAP>
 __device__ __forceinline__ void add_pair(const ForceArgs &a, double xi, double yi, double zi,
                                          double xj, double yj, double zj, int32_t j, bool valid,
                                          int ti, const Coef &c1, const double *tab, Acc &s) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-  if constexpr (WRAP) {
-    dx = min_image(dx, a.b.L[0], a.b.invL[0]);
-    dy = min_image(dy, a.b.L[1], a.b.invL[1]);
-    dz = min_image(dz, a.b.L[2], a.b.invL[2]);
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if constexpr (WRAP) {  // min_image, keeping the shift
+    const double kx = __builtin_rint(dx * a.b.invL[0]);
+    const double ky = __builtin_rint(dy * a.b.invL[1]);
+    const double kz = __builtin_rint(dz * a.b.invL[2]);
+    dx = __builtin_fma(-kx, a.b.L[0], dx);
+    dy = __builtin_fma(-ky, a.b.L[1], dy);
+    dz = __builtin_fma(-kz, a.b.L[2], dz);
+    sx = -kx * a.b.L[0];
+    sy = -ky * a.b.L[1];
+    sz = -kz * a.b.L[2];
   }
   const double r2 = dist2(dx, dy, dz);
   if (valid && r2 < a.rc2) {
@@ -158,14 +173,28 @@ __device__ __forceinline__ void add_pair(const ForceArgs &a, double xi, double y
     s.fz += p.fz;
     if constexpr (EV) {
       s.e += p.u;
-      s.wxx = __builtin_fma(dx, p.fx, s.wxx);
-      s.wyy = __builtin_fma(dy, p.fy, s.wyy);
-      s.wzz = __builtin_fma(dz, p.fz, s.wzz);
-      s.wxy = __builtin_fma(dx, p.fy, s.wxy);
-      s.wxz = __builtin_fma(dx, p.fz, s.wxz);
-      s.wyz = __builtin_fma(dy, p.fz, s.wyz);
+      if constexpr (WRAP) {
+        s.wxx = __builtin_fma(sx, p.fx, s.wxx);
+        s.wyy = __builtin_fma(sy, p.fy, s.wyy);
+        s.wzz = __builtin_fma(sz, p.fz, s.wzz);
+        s.wxy = __builtin_fma(sx, p.fy, s.wxy);
+        s.wxz = __builtin_fma(sx, p.fz, s.wxz);
+        s.wyz = __builtin_fma(sy, p.fz, s.wyz);
+      }
     }
   }
+}
+
+// The per-lane x_i (x) F term of the virial (see add_pair), with the lane's
+// part of F_i; called once per lane after its row, before any team sums.
+__device__ __forceinline__ void add_xf(double xi, double yi, double zi, Acc &s) {
+  const double x2 = 2.0 * xi, y2 = 2.0 * yi, z2 = 2.0 * zi;
+  s.wxx = __builtin_fma(x2, s.fx, s.wxx);
+  s.wyy = __builtin_fma(y2, s.fy, s.wyy);
+  s.wzz = __builtin_fma(z2, s.fz, s.wzz);
+  s.wxy = __builtin_fma(x2, s.fy, s.wxy);
+  s.wxz = __builtin_fma(x2, s.fz, s.wxz);
+  s.wyz = __builtin_fma(y2, s.fz, s.wyz);
 }
 
 // Walk atom i's row in groups of U slots: the U index loads, then the U
@@ -280,6 +309,7 @@ __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a
       walk_row<MIXED, T1, EV, U, false, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     else
       walk_row<MIXED, T1, EV, U, true, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+    if constexpr (EV) add_xf(xi, yi, zi, s);
   }
   const double e_lane = s.e;
   if constexpr (TEAM > 1) {
@@ -497,6 +527,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
       walk(std::false_type{});
     else
       walk(std::true_type{});
+    if constexpr (EV) add_xf(xi, yi, zi, s);
   }
   if constexpr (TEAM > 1) {
 #pragma unroll
