@@ -1,8 +1,10 @@
-"""Seeded synthetic inputs for the short-range Lennard-Jones MD hot path.
+"""Seeded synthetic inputs for the short-range Lennard-Jones MD hot path and the
+SPH pass built on the same lists.
 
 This module only draws inputs: an fcc lattice at a given reduced density,
 uniform positional jitter, Maxwell velocities, a 50/50 two-type assignment and
-per-type-pair (epsilon, sigma) draws.  It holds none of the method's
+per-type-pair (epsilon, sigma) draws; for SPH a jittered simple-cubic lattice
+with small Gaussian velocities.  It holds none of the method's
 arithmetic (no distances, forces, neighbor tests or integration) and imports
 neither the oracle nor the HIP package; both of those consume what it returns.
 
@@ -163,3 +165,67 @@ def random_gas(n: int, L, seed: int) -> np.ndarray:
     L = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
     g = np.random.Generator(np.random.PCG64(seed))
     return _into_box(g.uniform(0.0, 1.0, size=(n, 3)) * L, L)
+
+
+@dataclasses.dataclass(frozen=True)
+class SphWorkload:
+    """Weakly compressible SPH fluid at rest density 1: a simple-cubic lattice of
+    spacing 1 (particle mass 1), jittered, smoothing length h = 1.3 spacings
+    (support 2.6, about 74 neighbours inside it), sound speed 10."""
+    name: str
+    index: int              # seeds derive from SEED_BASE + 100 + index
+    cells: int              # particles per box edge
+    h: float = 1.3
+    mass: float = 1.0
+    c0: float = 10.0
+    rho0: float = 1.0
+    skin: float = 0.4
+    dt: float = 0.01
+    rebuild_every: int = 10
+    jitter: float = 0.1     # uniform positional jitter, spacings
+    vel: float = 0.2        # Gaussian velocity scale per component
+    steps: int = 0
+
+    @property
+    def natoms(self) -> int:
+        return self.cells ** 3
+
+    @property
+    def support(self) -> float:
+        return 2.0 * self.h
+
+    @property
+    def rlist(self) -> float:
+        return self.support + self.skin
+
+    @property
+    def box(self) -> np.ndarray:
+        return np.full(3, float(self.cells))
+
+
+SPH_WORKLOADS = {
+    "sph4k": SphWorkload("sph4k", 0, cells=16, steps=50),
+    "sph32k": SphWorkload("sph32k", 1, cells=32, steps=100),
+    "sph512k": SphWorkload("sph512k", 2, cells=80, steps=500),
+}
+
+
+def sph_rng(workload: SphWorkload, stream: int) -> np.random.Generator:
+    """PCG64 stream: 0 jitter, 1 velocities."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 100 + 10 * workload.index + stream))
+
+
+def sph_positions(workload: SphWorkload) -> np.ndarray:
+    """Jittered simple-cubic positions in [0, L)^3, FP64 [N, 3], loop order ix, iy, iz."""
+    idx = np.arange(workload.cells, dtype=np.float64)
+    ix, iy, iz = np.meshgrid(idx, idx, idx, indexing="ij")
+    x = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1) + 0.5
+    if workload.jitter > 0.0:
+        x = x + sph_rng(workload, 0).uniform(-workload.jitter, workload.jitter, size=x.shape)
+    return _into_box(x, workload.box)
+
+
+def sph_velocities(workload: SphWorkload) -> np.ndarray:
+    """Gaussian velocities of scale `vel` per component, zero mean."""
+    v = sph_rng(workload, 1).normal(0.0, workload.vel, size=(workload.natoms, 3))
+    return v - v.mean(axis=0)

@@ -5,3 +5,4 @@ this package.  It never imports the HIP package and the HIP package never
 imports it.
 """
 from .oracle import *  # noqa: F401,F403
+from .sph import *  # noqa: F401,F403,E402

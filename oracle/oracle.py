@@ -33,9 +33,9 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            src = os.path.join(_HERE, "oracle.c")
+            srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "sph.c")]
             if (not os.path.exists(_LIB_PATH)
-                    or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src)):
+                    or os.path.getmtime(_LIB_PATH) < max(map(os.path.getmtime, srcs))):
                 from . import build as _b
                 _b.build()
             L = ctypes.CDLL(_LIB_PATH)
@@ -53,6 +53,9 @@ def lib():
             L.orc_kick_drift.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _VP]
             L.orc_kick.argtypes = [_i64, _D, _D, _dbl, _dbl]
             L.orc_num_threads.restype = ctypes.c_int
+            L.orc_sph_kernel.argtypes = [_i64, _D, _dbl, _VP, _VP]
+            L.orc_sph_density.argtypes = [_i64, _D, _D, _dbl, _dbl, _i64, _VP, _D]
+            L.orc_sph_accel.argtypes = [_i64, _D, _D, _dbl, _dbl, _dbl, _dbl, _D, _i64, _VP, _D]
             _lib = L
     return _lib
 
