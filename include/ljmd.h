@@ -19,6 +19,9 @@
  *   ljmd_list_to_csr, ljmd_compute_forces_csr
  *                         compressed list form and team-per-atom traversal
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
+ *   ljmd_sph_density, ljmd_sph_accel
+ *                         SPH density summation and pressure acceleration over
+ *                         the same lists (second short-range pair kernel)
  *
  * plus a few helpers (grid, workspace sizes, errors) and the elementwise
  * steps of the discrete trajectory adjoint.
@@ -80,10 +83,11 @@ extern "C" {
 #define LJMD_OP_LOSS 4
 #define LJMD_OP_CSR 5        /* ljmd_list_to_csr */
 #define LJMD_OP_FORCES_CSR 6 /* ljmd_compute_forces_csr (any team) */
+#define LJMD_OP_SPH 7        /* ljmd_sph_density (with u_total), ljmd_sph_accel */
 
 #define LJMD_MAX_TYPES 8
-#define LJMD_TILE 64
-#define LJMD_MAX_TEAM 16 /* largest team (lanes per atom) of ljmd_compute_forces_csr */ /* atoms per neighbor-list tile: one wavefront */
+#define LJMD_TILE 64     /* atoms per neighbor-list tile: one wavefront */
+#define LJMD_MAX_TEAM 16 /* largest team (lanes per atom) of ljmd_compute_forces_csr */
 
 typedef struct {
   double L[3]; /* box edges; periodic in all three dimensions, origin at 0 */
@@ -167,7 +171,7 @@ int ljmd_build_neighbors(const ljmd_box *box, double rlist, int kind, int64_t n,
  *   ev = { E = sum_i e_i, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz },  W = 1/2 sum_i sum_j d_ij (s d_ij)^T
  * (truncated, unshifted; one absolute rc for every type pair).
  *   precision  LJMD_FP64 or LJMD_MIXED
- *   kind       list kind built by ljmd_build_neighbors.  FULL: one lane per
+ *   kind       list kind built by ljmd_build_neighbors.  FULL: two lanes per
  *              atom, no atomics, bitwise deterministic.  HALF: Newton's third
  *              law with FP64 atomic updates (summation order not fixed).
  *   ntypes     1..LJMD_MAX_TYPES; eps_packed/sigma_packed: device FP64
@@ -286,6 +290,39 @@ int ljmd_compute_forces_csr(const ljmd_box *box, int precision, double rc, int32
                             const double *x, const int32_t *type, const int64_t *offsets,
                             const int32_t *csr, int32_t team, double *F, double *e_atom,
                             double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_sph_density, ljmd_sph_accel -- smoothed-particle hydrodynamics over the
+ * same binned full lists (paper: SPH is, beside MD, a user of the short-range
+ * particle-particle sub-motif and of Verlet neighbor lists -- Introduction;
+ * Cabana "Neighbor List Creation").  The paper prints no SPH equations; the
+ * textbook forms are used, all in FP64:
+ *   cubic-spline kernel (Monaghan & Lattanzio 1985), support 2h, q = r/h:
+ *     W(r) = w(q)/(pi h^3), w = 1 - 3/2 q^2 + 3/4 q^3 (q < 1), 1/4 (2-q)^3 (1 <= q < 2), 0 beyond
+ *   rho_i = m W(0) + sum_{j in row i, r_ij^2 < (2h)^2} m W(r_ij)
+ *   p = c0^2 (rho - rho0)
+ *   a_i = - sum_j m (p_i/rho_i^2 + p_j/rho_j^2) W'(r_ij)/r_ij d_ij   (Monaghan 1992,
+ *         no artificial viscosity; d_ij = minimum-image x_i - x_j)
+ *   U = sum_i m c0^2 (ln(rho_i/rho0) + rho0/rho_i - 1), so that m a_i = -dU/dx_i.
+ * The list (nbr, nnbr, maxn) is a FULL list from ljmd_build_neighbors with
+ * rlist >= 2h over the same sorted positions x; pairs farther than 2h are
+ * skipped, pairs missing from the list are not seen.  Summation order is fixed:
+ * results are bitwise reproducible.
+ *   h, mass, rho0 > 0; c0 >= 0; 2h <= (1/2 - 1e-9) min(L) (else LJMD_EBOX)
+ *   rho      [n] overwritten (density pass); read by the acceleration pass
+ *            (values from the density pass are >= m/(pi h^3) > 0)
+ *   u_total  device FP64 scalar receiving U, or NULL
+ *   acc      [n][3] overwritten with a_i
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_SPH, n, 0, 0) bytes: the density pass
+ *            needs it only when u_total is given; the acceleration pass always
+ *            (n > 0) and requires it 32-byte aligned (LJMD_EINVAL otherwise)
+ */
+int ljmd_sph_density(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
+                     const double *x, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                     double *rho, double *u_total, void *ws, size_t ws_bytes, void *stream);
+int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
+                   const double *x, const double *rho, const int32_t *nbr, const int32_t *nnbr,
+                   int32_t maxn, double *acc, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- elementwise steps of the discrete velocity-Verlet adjoint ----
  *

@@ -40,6 +40,13 @@ int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, c
                       const double *sig, int64_t n, const double *x, const int32_t *type,
                       const int64_t *offsets, const int32_t *csr, int team, double *F,
                       double *e_atom, double *ev, void *ws, hipStream_t st);
+size_t sph_workspace(int64_t n);
+int launch_sph_density(const BoxK &b, double h, double mass, double c0, double rho0, int64_t n,
+                       const double *x, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                       double *rho, double *u_total, void *ws, hipStream_t st);
+int launch_sph_accel(const BoxK &b, double h, double mass, double c0, double rho0, int64_t n,
+                     const double *x, const double *rho, const int32_t *nbr,
+                     const int32_t *nnbr, int32_t maxn, double *acc, void *ws, hipStream_t st);
 size_t stream_workspace(int64_t n);
 int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n, double *x,
                      double *v, const double *F, double *ke, void *ws, hipStream_t st);
@@ -180,6 +187,7 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
     case LJMD_OP_LOSS: return stream_workspace(n);
     case LJMD_OP_CSR: return csr_workspace(n);
     case LJMD_OP_FORCES_CSR: return csr_force_workspace(n);
+    case LJMD_OP_SPH: return sph_workspace(n);
     default: return 0;
   }
 }
@@ -243,6 +251,42 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
   LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? force_workspace(n) : 0));
   return launch_forces(make_box(box), precision, kind, rc, ntypes, eps_packed, sigma_packed, n, x,
                        type, nbr, nnbr, maxn, F, e_atom, ev, ws, (hipStream_t)stream);
+}
+
+static int check_sph(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
+                     const double *x, const int32_t *nbr, const int32_t *nnbr, int32_t maxn) {
+  LJMD_TRY(check_box(box));
+  if (!(h > 0.0) || !isfinite(h)) return set_error(LJMD_EINVAL, "h = %g must be > 0", h);
+  LJMD_TRY(check_cutoff(box, 2.0 * h, "2h"));
+  LJMD_TRY(check_n(n));
+  if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g must be > 0", mass);
+  if (!(c0 >= 0.0) || !isfinite(c0)) return set_error(LJMD_EINVAL, "c0 = %g must be >= 0", c0);
+  if (!(rho0 > 0.0) || !isfinite(rho0)) return set_error(LJMD_EINVAL, "rho0 = %g must be > 0", rho0);
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (n > 0 && (!x || !nbr || !nnbr)) return set_error(LJMD_EINVAL, "x/nbr/nnbr is NULL");
+  return LJMD_OK;
+}
+
+int ljmd_sph_density(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
+                     const double *x, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                     double *rho, double *u_total, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_sph(box, h, mass, c0, rho0, n, x, nbr, nnbr, maxn));
+  if (n > 0 && !rho) return set_error(LJMD_EINVAL, "rho is NULL");
+  LJMD_TRY(check_ws(ws, ws_bytes, u_total ? sph_workspace(n) : 0));
+  return launch_sph_density(make_box(box), h, mass, c0, rho0, n, x, nbr, nnbr, maxn, rho, u_total,
+                            ws, (hipStream_t)stream);
+}
+
+int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
+                   const double *x, const double *rho, const int32_t *nbr, const int32_t *nnbr,
+                   int32_t maxn, double *acc, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_sph(box, h, mass, c0, rho0, n, x, nbr, nnbr, maxn));
+  if (n > 0 && (!rho || !acc)) return set_error(LJMD_EINVAL, "rho/acc is NULL");
+  LJMD_TRY(check_ws(ws, ws_bytes, n > 0 ? sph_workspace(n) : 0));
+  if (n > 0 && ((uintptr_t)ws & 31u) != 0)
+    return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
+  return launch_sph_accel(make_box(box), h, mass, c0, rho0, n, x, rho, nbr, nnbr, maxn, acc, ws,
+                          (hipStream_t)stream);
 }
 
 int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
                    MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
-                   OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, TILE, LjmdError, make_box)
+                   OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_SPH, TILE, LjmdError,
+                   make_box)
 
 
 def _ptr(t):
@@ -359,3 +360,49 @@ def _ntypes(eps) -> int:
     if t * (t + 1) // 2 != p or not 1 <= t <= MAX_TYPES:
         raise ValueError(f"packed parameter length {p} is not T(T+1)/2 with 1 <= T <= {MAX_TYPES}")
     return t
+
+
+def _sph_list(x, nbr, nnbr, maxn):
+    n = x.shape[0]
+    _need(x, "x", torch.float64, (n, 3))
+    _need(nbr, "nbr", torch.int32, None, x.device)
+    _need(nnbr, "nnbr", torch.int32, (n,), x.device)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    return n, x.device
+
+
+def sph_density(L, h, mass, c0, rho0, x, nbr, nnbr, maxn, rho=None, u_total=None,
+                want_energy=False, ws=None):
+    """SPH density of every particle over a FULL list with rlist >= 2h; with want_energy
+    (or u_total given) also U = sum m u(rho) into the one-element u_total."""
+    n, dev = _sph_list(x, nbr, nnbr, maxn)
+    if rho is None:
+        rho = torch.empty(n, dtype=torch.float64, device=dev)
+    if want_energy and u_total is None:
+        u_total = torch.empty(1, dtype=torch.float64, device=dev)
+    _need(rho, "rho", torch.float64, (n,), dev)
+    _need(u_total, "u_total", torch.float64, (1,), dev)
+    ws, need = _ws(OP_SPH, n, dev, ws=ws) if u_total is not None else (None, 0)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_sph_density(
+        ctypes.byref(b), float(h), float(mass), float(c0), float(rho0), n, _ptr(x), _ptr(nbr),
+        _ptr(nnbr), int(maxn), _ptr(rho), _ptr(u_total), _ptr(ws), need, _stream(dev)),
+        "ljmd_sph_density")
+    return rho, u_total
+
+
+def sph_accel(L, h, mass, c0, rho0, x, rho, nbr, nnbr, maxn, acc=None, ws=None):
+    """Symmetric SPH pressure acceleration [n, 3] from the densities rho."""
+    n, dev = _sph_list(x, nbr, nnbr, maxn)
+    _need(rho, "rho", torch.float64, (n,), dev)
+    if acc is None:
+        acc = torch.empty_like(x)
+    _need(acc, "acc", torch.float64, (n, 3), dev)
+    ws, need = _ws(OP_SPH, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_sph_accel(
+        ctypes.byref(b), float(h), float(mass), float(c0), float(rho0), n, _ptr(x), _ptr(rho),
+        _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(acc), _ptr(ws), need, _stream(dev)),
+        "ljmd_sph_accel")
+    return acc

@@ -48,6 +48,7 @@ def test_workspace_sizes(lib):
     assert W(lib.OP_BIN, 1000, 100, 1) >= 4 * (2 * 100 + 2 * 1000)
     assert W(lib.OP_FORCES, 500000, 0, 1) >= 8 * 7 * (500000 // 256)
     assert W(lib.OP_BACKWARD, 1000, 0, 2) >= W(lib.OP_BACKWARD, 1000, 0, 1)
+    assert W(lib.OP_SPH, 1000, 0, 1) >= 32 * 1000
     assert W(99, 10, 10, 1) == 0
 
 
@@ -132,6 +133,30 @@ def test_validation_rejects_bad_arguments(lib):
                 8, fake, fake, fake, fake, 2, fake, 1 << 20, None) == lib.EINVAL
     assert call(lib, "ljmd_force_backward", bb, 0, 2.5, 1, fake, fake, 10, fake, None, fake, fake,
                 8, fake, fake, None, fake, 0, fake, 1 << 20, None) == lib.EINVAL
+    # SPH: h <= 0, 2h too large for the box, bad mass / c0 / rho0, missing outputs,
+    # workspace missing, misaligned workspace
+    sargs = lambda h, m, c0, r0: (bb, h, m, c0, r0, 10, fake, fake, fake, 8)
+    assert call(lib, "ljmd_sph_density", *sargs(0.0, 1.0, 10.0, 1.0), fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_density", *sargs(2.6, 1.0, 10.0, 1.0), fake, None, None, 0,
+                None) == lib.EBOX
+    assert call(lib, "ljmd_sph_density", *sargs(1.3, 0.0, 10.0, 1.0), fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_density", *sargs(1.3, 1.0, -1.0, 1.0), fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_density", *sargs(1.3, 1.0, 10.0, 0.0), fake, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_density", *sargs(1.3, 1.0, 10.0, 1.0), None, None, None, 0,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_density", *sargs(1.3, 1.0, 10.0, 1.0), fake, fake, None, 0,
+                None) == lib.EWORKSPACE
+    assert call(lib, "ljmd_sph_accel", bb, 1.3, 1.0, 10.0, 1.0, 10, fake, fake, fake, fake, 8,
+                None, fake, 1 << 20, None) == lib.EINVAL
+    assert call(lib, "ljmd_sph_accel", bb, 1.3, 1.0, 10.0, 1.0, 10, fake, fake, fake, fake, 8,
+                fake, None, 0, None) == lib.EWORKSPACE
+    assert call(lib, "ljmd_sph_accel", bb, 1.3, 1.0, 10.0, 1.0, 10, fake, fake, fake, fake, 8,
+                fake, ctypes.c_void_p(4096 + 16), 1 << 20, None) == lib.EINVAL
+    assert b"aligned" in lib.load().ljmd_last_error()
     assert call(lib, "ljmd_scatter_rows", 10, 0, fake, fake, fake, None) == lib.EINVAL
     assert call(lib, "ljmd_gather_rows", -1, 3, fake, fake, fake, None) == lib.EINVAL
     assert call(lib, "ljmd_traj_loss", bb, 10, fake, fake, fake, None, fake, 1 << 20,
