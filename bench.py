@@ -51,6 +51,8 @@ def parse():
                     help="time the headline path only (no FP64 run, no bwd/fwd ratios)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target length of the oracle's CPU sample")
+    ap.add_argument("--sph-only", action="store_true",
+                    help="run only the SPH leg (512,000 particles) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (x5), to calibrate HBM "
                          "byte counters")
@@ -261,6 +263,45 @@ def shard_share(dev, steps=200, warmup=40):
             "step_launch_us": round(statistics.mean(fms) * 1e3, 3)}
 
 
+def sph_bench(dev, steps=300, warmup=50, reps=50):
+    """SPH over the same bins and lists: the 512,000-particle lattice fluid (h 1.3,
+    support 2.6, skin 0.4, rebuild every 10 steps), velocity-Verlet steps with the
+    density and pressure passes, then each pass alone (HIP events).  Algorithmic
+    bytes per particle: density 4 nbar + 4 (count) + 24 (x) + 8 (rho written);
+    acceleration 32 + 32 (packing x, rho into records) + 4 nbar + 4 + 32 (own
+    record) + 24 (a written); neighbour records are gathered through L1/L2."""
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import ops, sph
+    w = li.SPH_WORKLOADS["sph512k"]
+    sim = sph.SPHSim(w.box, w.h, mass=w.mass, c0=w.c0, rho0=w.rho0, skin=w.skin, dt=w.dt,
+                     rebuild_every=w.rebuild_every, device=dev)
+    sim.load(li.sph_positions(w), li.sph_velocities(w))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nl, n = sim.nl, sim.n
+    nb = float(nl.nnbr.double().mean().item())
+    td = event_time(lambda: ops.sph_density(sim.L, sim.h, sim.mass, sim.c0, sim.rho0, sim.x,
+                                            nl.nbr, nl.nnbr, nl.maxn, rho=sim.rho), reps)
+    ta = event_time(lambda: ops.sph_accel(sim.L, sim.h, sim.mass, sim.c0, sim.rho0, sim.x,
+                                          sim.rho, nl.nbr, nl.nnbr, nl.maxn, acc=sim.acc,
+                                          ws=sim.ws), reps)
+    bd = n * (4.0 * nb + 36)
+    ba = n * (4.0 * nb + 124)
+    return {"natoms": n, "steps": steps, "value": round(n * steps / t, 1),
+            "unit": "particle-steps/s", "ms_per_step": round(t * 1e3 / steps, 5),
+            "mean_list_length": round(nb, 3), "rebuild_every": w.rebuild_every,
+            "density_us": round(td * 1e3, 2), "accel_us": round(ta * 1e3, 2),
+            "density_GBps": round(bd / (td * 1e-3) / 1e9, 1),
+            "accel_GBps": round(ba / (ta * 1e-3) / 1e9, 1),
+            "density_frac": round(bd / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "accel_frac": round(ba / (ta * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(w, s, target_s):
     """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input."""
     import numpy as np
@@ -285,8 +326,8 @@ def cpu_baseline(w, s, target_s):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(spatial decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(the spatial decomposition across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
@@ -298,6 +339,9 @@ def main():
 
     dev = torch.device("cuda:0")
     _lib.load()
+    if args.sph_only:
+        print(json.dumps({"sph_512k": sph_bench(dev)}), flush=True)
+        return
     w = li.WORKLOADS[args.workload]
     s = li.make_system(w)
     n = w.natoms
@@ -359,6 +403,8 @@ def main():
                                                    (statistics.mean(f2ms) * 1e-3) / 1e9, 2)}
         log(f"[bench] 2M atoms: {t2 * 1e3 / w2.steps:.4f} ms/step")
         del sim2, s2
+        line["sph_512k"] = sph_bench(dev)
+        log(f"[bench] SPH 512k: {line['sph_512k']}")
         line["shard_share_2x2x2"] = shard_share(dev)
         log(f"[bench] one 2x2x2 shard: {line['shard_share_2x2x2']}")
         log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")

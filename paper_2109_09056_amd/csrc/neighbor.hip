@@ -18,11 +18,17 @@ namespace ljmd {
 
 namespace {
 
-constexpr int kSlots = 12;  // register slots: up to 768 candidates staged
+// Two shapes of the build kernel.  Standard: 12 register slots (up to 768
+// candidates staged) and rows of up to 128 entries buffered in LDS.  Dense
+// (chosen when maxn > 128, i.e. long rows and so crowded stencils): 16 slots
+// (1024 candidates) and rows of up to 256 entries, at twice the LDS.
+constexpr int kSlots = 12;
+constexpr int kRowCap = 128;
+constexpr int kDenseSlots = 16;
+constexpr int kDenseRowCap = 256;
 constexpr int kBatch = 16;  // home atoms whose rows are buffered in LDS at once
 constexpr int kFlushRows = kWave / kBatch;  // list rows of a batch written per store instruction
-constexpr int kRowCap = 128;              // longest row buffered in LDS
-constexpr int kRowStride = kRowCap + 1;   // odd stride: lanes reading row k hit distinct banks
+// LDS row stride ROWCAP + 1 (odd): lanes reading entry k of different rows hit distinct banks
 
 __global__ void k_fill_scalar(int32_t *p, int32_t val) { *p = val; }
 
@@ -94,9 +100,9 @@ __device__ __forceinline__ int32_t locate(int32_t t, const int32_t *rs, const in
   return rs[r] + (t - pre[r]);
 }
 
-// Register-staged build of one cell's rows (candidates <= kSlots * 64).  BUF:
-// rows are compacted in LDS (maxn <= kRowCap) rather than stored directly.
-template <bool HALF, bool WRAP, bool BUF>
+// Register-staged build of one cell's rows (candidates <= SLOTS * 64).  BUF:
+// rows are compacted in LDS (maxn <= ROWCAP) rather than stored directly.
+template <bool HALF, bool WRAP, bool BUF, int SLOTS, int ROWCAP>
 __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const double *__restrict__ x,
                                              int32_t h0, int32_t h1, int32_t total, int nslot,
                                              const int32_t *rs, const int32_t *pre, int32_t maxn,
@@ -105,10 +111,11 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   const int lane = threadIdx.x & (kWave - 1);
   const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
   const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
-  double qx[kSlots], qy[kSlots], qz[kSlots];
-  int32_t qj[kSlots];
+  constexpr int kRowStride = ROWCAP + 1;
+  double qx[SLOTS], qy[SLOTS], qz[SLOTS];
+  int32_t qj[SLOTS];
 #pragma unroll
-  for (int r = 0; r < kSlots; ++r) {
+  for (int r = 0; r < SLOTS; ++r) {
     const int32_t t = r * kWave + lane;
     qj[r] = -1;
     qx[r] = qy[r] = qz[r] = 0.0;
@@ -146,7 +153,7 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
       int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
       int32_t base = 0;
 #pragma unroll
-      for (int r = 0; r < kSlots; ++r) {
+      for (int r = 0; r < SLOTS; ++r) {
         if (r < nslot) {
           double dx = xi - qx[r], dy = yi - qy[r], dz = zi - qz[r];
           if constexpr (WRAP) {
@@ -192,7 +199,7 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   }
 }
 
-template <bool HALF>
+template <bool HALF, int SLOTS, int ROWCAP>
 __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
                                                  const double *__restrict__ x,
                                                  const int32_t *__restrict__ cell_start,
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
                                                  int32_t *__restrict__ max_count) {
   __shared__ int32_t rs[27];
   __shared__ int32_t pre[28];
-  __shared__ int32_t rowbuf[kBatch * kRowStride];
+  __shared__ int32_t rowbuf[kBatch * (ROWCAP + 1)];
   __shared__ int32_t rowcnt[kBatch];
   const int lane = threadIdx.x;
   const int32_t c = xcd_block(blockIdx.x, gridDim.x);
@@ -222,11 +229,11 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
     for (int k = 0; k < 3; ++k)
       wrap |= g.nc[k] < 4 || cc[k] == 0 || cc[k] == g.nc[k] - 1;
   }
-  if (nslot <= kSlots) {
-#define LJMD_STAGED(W, B)                                                                   \
-  build_staged<HALF, W, B>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, nnbr, rowbuf, \
-                           rowcnt, maxc)
-    if (maxn <= kRowCap) {
+  if (nslot <= SLOTS) {
+#define LJMD_STAGED(W, B)                                                                  \
+  build_staged<HALF, W, B, SLOTS, ROWCAP>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, \
+                                          nnbr, rowbuf, rowcnt, maxc)
+    if (maxn <= ROWCAP) {
       if (wrap) LJMD_STAGED(true, true); else LJMD_STAGED(false, true);
     } else {
       if (wrap) LJMD_STAGED(true, false); else LJMD_STAGED(false, false);
@@ -274,12 +281,22 @@ int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t 
   k_fill_scalar<<<1, 1, 0, st>>>(max_count, 0);
   if (n > 0) {
     const double rl2 = rlist * rlist;
-    if (kind == LJMD_HALF)
-      k_build<true><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn, nbr, nnbr,
-                                               max_count);
-    else
-      k_build<false><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn, nbr, nnbr,
-                                                max_count);
+    const bool half = kind == LJMD_HALF;
+    if (maxn <= kRowCap) {
+      if (half)
+        k_build<true, kSlots, kRowCap><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn,
+                                                                  nbr, nnbr, max_count);
+      else
+        k_build<false, kSlots, kRowCap><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start,
+                                                                   maxn, nbr, nnbr, max_count);
+    } else {
+      if (half)
+        k_build<true, kDenseSlots, kDenseRowCap><<<g.ncells, kWave, 0, st>>>(
+            g, b, rl2, x, cell_start, maxn, nbr, nnbr, max_count);
+      else
+        k_build<false, kDenseSlots, kDenseRowCap><<<g.ncells, kWave, 0, st>>>(
+            g, b, rl2, x, cell_start, maxn, nbr, nnbr, max_count);
+    }
   }
   return check_launch("ljmd_build_neighbors");
 }

@@ -156,6 +156,28 @@ def test_neighbor_sets_match_oracle(dev, orc, name, kind):
         assert rows_total == want.shape[0]
 
 
+@pytest.mark.parametrize("kind", ["full", "half"])
+@pytest.mark.parametrize("case", ["sph4k", "lj32k"])
+def test_neighbor_sets_dense_build_shape(dev, orc, case, kind):
+    """Row capacity above 128 selects the build's dense shape (16 register slots, rows of
+    up to 256 entries compacted in LDS): the SPH fluid at rlist 3.0 (~790 candidates per
+    stencil) and the LJ liquid, both against the oracle."""
+    from paper_2109_09056_amd import ops
+    if case == "sph4k":
+        w = li.SPH_WORKLOADS[case]
+        x, L, rl = li.sph_positions(w), w.box, w.rlist
+    else:
+        w = li.WORKLOADS[case]
+        x, L, rl = li.positions(w), w.box, w.rlist
+    k = ops.FULL if kind == "full" else ops.HALF
+    nl, ids, _ = gpu_lists(dev, x, L, rl, k, maxn=200)
+    assert nl.maxn == 200 and nl.overflows == 0
+    got = gpu_pairs_by_id(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn,
+                          ids.cpu().numpy(), half=(kind == "half"))
+    off, nb = orc.neighbor_lists(x, L, rl)
+    assert np.array_equal(got, oracle_pairs(off, nb, half=(kind == "half")))
+
+
 def test_neighbor_capacity_overflow_reported(dev, orc):
     from paper_2109_09056_amd import ops
     w = li.WORKLOADS["lj256"]
