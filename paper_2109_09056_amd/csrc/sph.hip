@@ -59,9 +59,18 @@ __device__ __forceinline__ const double4 *rec_of(const double4 *xp, int32_t j) {
     return (const double4 *)((const char *)xp + ((uint32_t)j << 5));
 }
 
+// q = r/h and 1/q (only used where q >= 1).  Measured against r^-1 from the
+// hardware reciprocal square root with Newton steps, this form was as fast for
+// the density pass and faster for the acceleration pass.
+__device__ __forceinline__ void q_of(double r2, const SphArgs &a, double &q, double &hq) {
+  q = __builtin_sqrt(r2) * a.inv_h;
+  hq = recip64(q);
+}
+
 // w(q) inside the support, 0 outside or on padding slots
 __device__ __forceinline__ double spline_w(double r2, bool ok, const SphArgs &a) {
-  const double q = __builtin_sqrt(r2) * a.inv_h;
+  double q, hq;
+  q_of(r2, a, q, hq);
   const double t = 2.0 - q;
   const double wi = __builtin_fma(q * q, __builtin_fma(0.75, q, -1.5), 1.0);
   const double wo = 0.25 * (t * t) * t;
@@ -71,10 +80,11 @@ __device__ __forceinline__ double spline_w(double r2, bool ok, const SphArgs &a)
 
 // g(q) inside the support, 0 outside or on padding slots
 __device__ __forceinline__ double spline_g(double r2, bool ok, const SphArgs &a) {
-  const double q = __builtin_sqrt(r2) * a.inv_h;
+  double q, hq;
+  q_of(r2, a, q, hq);
   const double t = 2.0 - q;
   const double gi = __builtin_fma(2.25, q, -3.0);
-  const double go = -0.75 * (t * t) * recip64(q);
+  const double go = -0.75 * (t * t) * hq;
   const double g = q < 1.0 ? gi : go;
   return ok && r2 < a.sup2 ? g : 0.0;
 }
@@ -93,14 +103,36 @@ __device__ __forceinline__ void disp(const SphArgs &a, double xi, double yi, dou
   }
 }
 
-// Sum of w over lane t's entries of the row (cnt of them, kStep ints apart).
+// Sum of w over lane t's entries of the row (cnt of them, kStep ints apart):
+// whole groups of U without masks, then one masked group.
 template <bool WRAP, bool WIDE>
 __device__ __forceinline__ double density_row(const SphArgs &a, const int32_t *row, int32_t cnt,
                                               double xi, double yi, double zi) {
   constexpr int U = kSphUnroll;
   constexpr int kStep = kSphTeam * kWave;
   double s = 0.0;
-  for (int32_t k = 0; k < cnt; k += U, row += U * kStep) {
+  const int32_t whole = cnt - cnt % U;
+  int32_t k = 0;
+  for (; k < whole; k += U, row += U * kStep) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = row[u * kStep];
+    double xj[U], yj[U], zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double *p = pos_of<WIDE>(a.x, j[u]);
+      xj[u] = p[0];
+      yj[u] = p[1];
+      zj[u] = p[2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double dx, dy, dz;
+      disp<WRAP>(a, xi, yi, zi, xj[u], yj[u], zj[u], dx, dy, dz);
+      s += spline_w(dist2(dx, dy, dz), true, a);
+    }
+  }
+  if (k < cnt) {
     int32_t j[U];
     bool ok[U];
 #pragma unroll
@@ -184,12 +216,36 @@ __global__ __launch_bounds__(256) void k_sph_pack(SphArgs a, double4 *xp) {
 }
 
 template <bool WRAP, bool WIDE>
+__device__ __forceinline__ void accel_pair(const SphArgs &a, const double4 &me, const double4 &o,
+                                           bool ok, double &ax, double &ay, double &az) {
+  double dx, dy, dz;
+  disp<WRAP>(a, me.x, me.y, me.z, o.x, o.y, o.z, dx, dy, dz);
+  const double c = (me.w + o.w) * spline_g(dist2(dx, dy, dz), ok, a);
+  ax = __builtin_fma(c, dx, ax);
+  ay = __builtin_fma(c, dy, ay);
+  az = __builtin_fma(c, dz, az);
+}
+
+// Lane t's entries of the row: whole groups of U without masks, then one masked group.
+template <bool WRAP, bool WIDE>
 __device__ __forceinline__ void accel_row(const SphArgs &a, const int32_t *row, int32_t cnt,
                                           const double4 &me, double &ax, double &ay,
                                           double &az) {
   constexpr int U = kSphUnroll;
   constexpr int kStep = kSphTeam * kWave;
-  for (int32_t k = 0; k < cnt; k += U, row += U * kStep) {
+  const int32_t whole = cnt - cnt % U;
+  int32_t k = 0;
+  for (; k < whole; k += U, row += U * kStep) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = row[u * kStep];
+    double4 o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) o[u] = *rec_of<WIDE>(a.xp, j[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) accel_pair<WRAP, WIDE>(a, me, o[u], true, ax, ay, az);
+  }
+  if (k < cnt) {
     int32_t j[U];
     bool ok[U];
 #pragma unroll
@@ -204,14 +260,7 @@ __device__ __forceinline__ void accel_row(const SphArgs &a, const int32_t *row, 
       if (ok[u]) o[u] = *rec_of<WIDE>(a.xp, j[u]);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      double dx, dy, dz;
-      disp<WRAP>(a, me.x, me.y, me.z, o[u].x, o[u].y, o[u].z, dx, dy, dz);
-      const double c = (me.w + o[u].w) * spline_g(dist2(dx, dy, dz), ok[u], a);
-      ax = __builtin_fma(c, dx, ax);
-      ay = __builtin_fma(c, dy, ay);
-      az = __builtin_fma(c, dz, az);
-    }
+    for (int u = 0; u < U; ++u) accel_pair<WRAP, WIDE>(a, me, o[u], ok[u], ax, ay, az);
   }
 }
 
