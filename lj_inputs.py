@@ -74,7 +74,8 @@ WORKLOADS = {
 
 
 def rng(workload: Workload, stream: int) -> np.random.Generator:
-    """PCG64 stream: 0 jitter, 1 velocities, 2 types, 3 parameters, 4 perturbation."""
+    """PCG64 stream: 0 jitter, 1 velocities, 2 types, 3 parameters, 4 perturbation,
+    5 charges."""
     return np.random.Generator(np.random.PCG64(SEED_BASE + workload.index + stream))
 
 
@@ -122,6 +123,32 @@ def types(workload: Workload, n: int | None = None) -> np.ndarray:
         for k in range(1, workload.ntypes):
             t[perm[k * per:(k + 1) * per]] = k
     return t
+
+
+def charges(workload: Workload, n: int | None = None) -> np.ndarray:
+    """Unit point charges for the long-range (SPME) path: +1 on exactly floor(N/2)
+    atoms chosen by a seeded permutation, -1 on the rest (neutral for even N)."""
+    n = workload.natoms if n is None else n
+    q = -np.ones(n)
+    q[rng(workload, 5).permutation(n)[:n // 2]] = 1.0
+    return q
+
+
+# SPME settings for the charged liquid: erfc(alpha rc) = 2.2e-5 at rc = 2.5, cubic
+# (order 4) B-splines, grid of a power of two points per edge with spacing <= 0.7 sigma
+EWALD_ALPHA = 1.2
+EWALD_ORDER = 4
+
+
+def ewald_grid(L) -> tuple[int, int, int]:
+    """Smallest power of two K >= L / 0.7 per edge (at least 8)."""
+    out = []
+    for v in np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)):
+        k = 8
+        while v / k > 0.7:
+            k *= 2
+        out.append(k)
+    return tuple(out)
 
 
 def npacked(ntypes: int) -> int:

@@ -6,3 +6,4 @@ imports it.
 """
 from .oracle import *  # noqa: F401,F403
 from .sph import *  # noqa: F401,F403,E402
+from .spme import *  # noqa: F401,F403,E402

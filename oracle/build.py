@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "sph.c")]
+SRCS = [os.path.join(HERE, f) for f in ("oracle.c", "sph.c", "ewald.c")]
 LIB = os.path.join(HERE, "liborc.so")
 
 

@@ -33,7 +33,7 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "sph.c")]
+            srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "sph.c", "ewald.c")]
             if (not os.path.exists(_LIB_PATH)
                     or os.path.getmtime(_LIB_PATH) < max(map(os.path.getmtime, srcs))):
                 from . import build as _b
@@ -56,6 +56,9 @@ def lib():
             L.orc_sph_kernel.argtypes = [_i64, _D, _dbl, _VP, _VP]
             L.orc_sph_density.argtypes = [_i64, _D, _D, _dbl, _dbl, _i64, _VP, _D]
             L.orc_sph_accel.argtypes = [_i64, _D, _D, _dbl, _dbl, _dbl, _dbl, _D, _i64, _VP, _D]
+            L.orc_ewald_direct.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _D]
+            L.orc_ewald_recip.argtypes = [_i64, _D, _D, _D, _dbl, ctypes.c_int, _D]
+            L.orc_ewald_recip.restype = _dbl
             _lib = L
     return _lib
 
