@@ -35,14 +35,17 @@ static double ew_min_image(double d, double L) {
   return d;
 }
 
-/* Direct-space part: per-particle energy halves e_dir[i] (sum_i = E_dir) and
- * forces F_dir [n][3]; all pairs with r < rc. */
+/* Direct-space part for rows sel[0..nsel) (all rows when sel is NULL; then
+ * nsel = n): per-particle energy halves e_dir[k] (their sum over all rows is
+ * E_dir) and forces F_dir[3k..3k+2] of particle sel[k]; all pairs with r < rc. */
 void orc_ewald_direct(int64_t n, const double *x, const double *q, const double L[3],
-                      double alpha, double rc, double *e_dir, double *F_dir) {
+                      double alpha, double rc, int64_t nsel, const int64_t *sel, double *e_dir,
+                      double *F_dir) {
   const double c = 2.0 * alpha / sqrt(kPiE);
   const double rc2 = rc * rc;
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t k = 0; k < nsel; ++k) {
+    const int64_t i = sel ? sel[k] : k;
     double e = 0.0, f[3] = {0.0, 0.0, 0.0};
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
@@ -61,10 +64,10 @@ void orc_ewald_direct(int64_t n, const double *x, const double *q, const double 
       f[1] += s * d[1];
       f[2] += s * d[2];
     }
-    e_dir[i] = e;
-    F_dir[3 * i] = f[0];
-    F_dir[3 * i + 1] = f[1];
-    F_dir[3 * i + 2] = f[2];
+    e_dir[k] = e;
+    F_dir[3 * k] = f[0];
+    F_dir[3 * k + 1] = f[1];
+    F_dir[3 * k + 2] = f[2];
   }
 }
 

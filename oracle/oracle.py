@@ -56,7 +56,7 @@ def lib():
             L.orc_sph_kernel.argtypes = [_i64, _D, _dbl, _VP, _VP]
             L.orc_sph_density.argtypes = [_i64, _D, _D, _dbl, _dbl, _i64, _VP, _D]
             L.orc_sph_accel.argtypes = [_i64, _D, _D, _dbl, _dbl, _dbl, _dbl, _D, _i64, _VP, _D]
-            L.orc_ewald_direct.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _D]
+            L.orc_ewald_direct.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _i64, _VP, _D, _D]
             L.orc_ewald_recip.argtypes = [_i64, _D, _D, _D, _dbl, ctypes.c_int, _D]
             L.orc_ewald_recip.restype = _dbl
             _lib = L

@@ -32,14 +32,17 @@ __all__ = ["ewald_direct", "ewald_recip", "ewald_self", "bspline", "spme_recip",
            "spme_grid_charge"]
 
 
-def ewald_direct(x, q, L, alpha, rc):
-    """(per-particle direct energies [n], direct forces [n, 3])."""
+def ewald_direct(x, q, L, alpha, rc, sel=None):
+    """(per-particle direct energies, direct forces [., 3]) of every particle or of the
+    rows in sel."""
     x = _f64(x)
     q = _f64(q)
     n = x.shape[0]
-    e = np.empty(n)
-    F = np.empty((n, 3))
-    lib().orc_ewald_direct(n, x, q, _box(L), float(alpha), float(rc), e, F)
+    s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    ns = n if s is None else s.size
+    e = np.empty(ns)
+    F = np.empty((ns, 3))
+    lib().orc_ewald_direct(n, x, q, _box(L), float(alpha), float(rc), ns, _ptr(s), e, F)
     return e, F
 
 
@@ -83,11 +86,16 @@ def _weights(x, L, K, n):
 def spme_grid_charge(x, q, L, K, n):
     """Q(k) on the K_0 x K_1 x K_2 grid (index order [k0, k1, k2])."""
     x = _f64(x)
+    q = _f64(q)
     idx, w, _ = _weights(x, L, K, n)
     Q = np.zeros(tuple(K))
-    for i in range(x.shape[0]):
-        wt = q[i] * w[i, 0][:, None, None] * w[i, 1][None, :, None] * w[i, 2][None, None, :]
-        np.add.at(Q, np.ix_(idx[i, 0], idx[i, 1], idx[i, 2]), wt)
+    # every particle's n^3 products q_i M(u_0 - k_0) M(u_1 - k_1) M(u_2 - k_2), added at their points
+    wt = q[:, None, None, None] * w[:, 0, :, None, None] * w[:, 1, None, :, None] * \
+        w[:, 2, None, None, :]
+    i0 = np.broadcast_to(idx[:, 0, :, None, None], wt.shape)
+    i1 = np.broadcast_to(idx[:, 1, None, :, None], wt.shape)
+    i2 = np.broadcast_to(idx[:, 2, None, None, :], wt.shape)
+    np.add.at(Q, (i0.ravel(), i1.ravel(), i2.ravel()), wt.ravel())
     return Q
 
 
@@ -98,8 +106,9 @@ def _bmod2(K, n):
     return 1.0 / np.abs(den) ** 2
 
 
-def spme_recip(x, q, L, alpha, K, n=4):
-    """(E_rec, F_rec [n_p, 3]) by SPME with grid K = (K0, K1, K2) and spline order n."""
+def spme_recip(x, q, L, alpha, K, n=4, sel=None):
+    """(E_rec, F_rec) by SPME with grid K = (K0, K1, K2) and spline order n; the forces
+    of every particle [n_p, 3], or of the rows in sel [len(sel), 3]."""
     x = _f64(x)
     q = _f64(q)
     L = np.asarray(L, dtype=np.float64)
@@ -118,13 +127,14 @@ def spme_recip(x, q, L, alpha, K, n=4):
     FQ = np.fft.fftn(Q)
     E = 0.5 * float(np.sum(B * C * np.abs(FQ) ** 2))
     phi = np.real(np.fft.ifftn(B * C * FQ)) * (K[0] * K[1] * K[2])
-    idx, w, dw = _weights(x, L, K, n)
-    F = np.empty_like(x)
+    rows = np.arange(x.shape[0]) if sel is None else np.asarray(sel, dtype=np.int64)
+    idx, w, dw = _weights(x[rows], L, K, n)
+    F = np.empty((rows.size, 3))
     Ka = np.asarray(K, dtype=np.float64)
-    for i in range(x.shape[0]):
+    for i in range(rows.size):
         P = phi[np.ix_(idx[i, 0], idx[i, 1], idx[i, 2])]
         g0 = np.einsum("a,b,c,abc->", dw[i, 0], w[i, 1], w[i, 2], P) * Ka[0] / L[0]
         g1 = np.einsum("a,b,c,abc->", w[i, 0], dw[i, 1], w[i, 2], P) * Ka[1] / L[1]
         g2 = np.einsum("a,b,c,abc->", w[i, 0], w[i, 1], dw[i, 2], P) * Ka[2] / L[2]
-        F[i] = -q[i] * np.array([g0, g1, g2])
+        F[i] = -q[rows[i]] * np.array([g0, g1, g2])
     return E, F
