@@ -22,6 +22,9 @@
  *   ljmd_sph_density, ljmd_sph_accel
  *                         SPH density summation and pressure acceleration over
  *                         the same lists (second short-range pair kernel)
+ * *   ljmd_ewald_real, ljmd_spme_recip
+ *                         long-range electrostatics: Ewald real space over the
+ *                         lists, smooth particle-mesh Ewald in reciprocal space
  *
  * plus a few helpers (grid, workspace sizes, errors) and the elementwise
  * steps of the discrete trajectory adjoint.
@@ -84,6 +87,9 @@ extern "C" {
 #define LJMD_OP_CSR 5        /* ljmd_list_to_csr */
 #define LJMD_OP_FORCES_CSR 6 /* ljmd_compute_forces_csr (any team) */
 #define LJMD_OP_SPH 7        /* ljmd_sph_density (with u_total), ljmd_sph_accel */
+#define LJMD_OP_EWALD_REAL 8 /* ljmd_ewald_real */
+#define LJMD_OP_SPME 9       /* ljmd_spme_recip; ncells = K[0]*K[1]*K[2] grid points */
+#define LJMD_SPME_MAX_GRID 256 /* largest grid edge of ljmd_spme_recip */
 
 #define LJMD_MAX_TYPES 8
 #define LJMD_TILE 64     /* atoms per neighbor-list tile: one wavefront */
@@ -323,6 +329,43 @@ int ljmd_sph_density(const ljmd_box *box, double h, double mass, double c0, doub
 int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
                    const double *x, const double *rho, const int32_t *nbr, const int32_t *nnbr,
                    int32_t maxn, double *acc, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_ewald_real, ljmd_spme_recip -- electrostatics of point charges by smooth
+ * particle-mesh Ewald (paper: CabanaMD's long-range forces -- real-space
+ * energies and forces through the neighbor parallel loops; reciprocal space by
+ * spline spreading of charge to a uniform grid, 3-D FFTs and a gradient kernel
+ * that gathers forces back; Cabana "Long Range Solvers", "Particle-Grid
+ * Interpolation").  The method is SPME as defined by Essmann et al. (1995),
+ * Gaussian units (k_e = 1), neutral system, conducting boundary, FP64:
+ *   E_dir  = 1/2 sum_i sum_{j in row i, r < rc} q_i q_j erfc(alpha r)/r
+ *   E_rec  = 1/2 sum_{m != 0} B(m) C(m) |F(Q)(m)|^2 with the order-n cardinal
+ *            B-spline charge grid Q on K[0] x K[1] x K[2] points (x fastest),
+ *            B(m) = prod_a |b_a(m_a)|^2, C(m) = exp(-pi^2 |m'|^2/alpha^2)/(pi V |m'|^2)
+ *   E_self = -alpha/sqrt(pi) sum_i q_i^2
+ * and the forces are minus the gradients of E_dir and E_rec.
+ *
+ * ljmd_ewald_real: the list is a FULL list (ljmd_build_neighbors, rlist >= rc)
+ *   over the same sorted x; q [n] charges in the same order.  F [n][3] receives
+ *   the direct-space forces (accumulate 0: overwritten, 1: added); e_total (device
+ *   FP64 scalar, or NULL) receives E_dir.  ws >= ljmd_workspace_bytes(
+ *   LJMD_OP_EWALD_REAL, n, 0, 0), 32-byte aligned.  Fixed summation order.
+ * ljmd_spme_recip: order 4, 6 or 8; K (host int32[3]) powers of two in
+ *   [8, LJMD_SPME_MAX_GRID]; x [n][3] in [0, L) (any order), q [n].  F receives
+ *   the reciprocal-space forces (accumulate as above); e_total (or NULL)
+ *   receives E_rec + E_self.  ws >= ljmd_workspace_bytes(LJMD_OP_SPME, n,
+ *   K[0]*K[1]*K[2], 0), 32-byte aligned; it holds the complex grid.  The charge
+ *   spreading uses FP64 atomic additions: results agree run to run to rounding,
+ *   not bit for bit.
+ *   alpha > 0; rc as for the other pair kernels (LJMD_EBOX if too large).
+ */
+int ljmd_ewald_real(const ljmd_box *box, double alpha, double rc, int64_t n, const double *x,
+                    const double *q, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                    double *F, double *e_total, int accumulate, void *ws, size_t ws_bytes,
+                    void *stream);
+int ljmd_spme_recip(const ljmd_box *box, double alpha, int32_t order, const int32_t K[3],
+                    int64_t n, const double *x, const double *q, double *F, double *e_total,
+                    int accumulate, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- elementwise steps of the discrete velocity-Verlet adjoint ----
  *

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libljmd.so")
 SOURCES = ["api.hip", "bin.hip", "neighbor.hip", "force.hip", "backward.hip", "integrate.hip",
-           "csr.hip", "sph.hip"]
+           "csr.hip", "sph.hip", "spme.hip"]
 ARCH = os.environ.get("LJMD_OFFLOAD_ARCH", "gfx950")
 
 

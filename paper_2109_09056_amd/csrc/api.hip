@@ -47,6 +47,14 @@ int launch_sph_density(const BoxK &b, double h, double mass, double c0, double r
 int launch_sph_accel(const BoxK &b, double h, double mass, double c0, double rho0, int64_t n,
                      const double *x, const double *rho, const int32_t *nbr,
                      const int32_t *nnbr, int32_t maxn, double *acc, void *ws, hipStream_t st);
+size_t ewald_real_workspace(int64_t n);
+size_t spme_workspace(int64_t n, int64_t npts);
+int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const double *x,
+                      const double *q, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                      double *F, double *e_total, int accumulate, void *ws, hipStream_t st);
+int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t K[3], int64_t n,
+                      const double *x, const double *q, double *F, double *e_total,
+                      int accumulate, void *ws, hipStream_t st);
 size_t stream_workspace(int64_t n);
 int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n, double *x,
                      double *v, const double *F, double *ke, void *ws, hipStream_t st);
@@ -188,6 +196,8 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
     case LJMD_OP_CSR: return csr_workspace(n);
     case LJMD_OP_FORCES_CSR: return csr_force_workspace(n);
     case LJMD_OP_SPH: return sph_workspace(n);
+    case LJMD_OP_EWALD_REAL: return ewald_real_workspace(n);
+    case LJMD_OP_SPME: return spme_workspace(n, ncells > 0 ? ncells : 1);
     default: return 0;
   }
 }
@@ -287,6 +297,48 @@ int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double
     return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
   return launch_sph_accel(make_box(box), h, mass, c0, rho0, n, x, rho, nbr, nnbr, maxn, acc, ws,
                           (hipStream_t)stream);
+}
+
+int ljmd_ewald_real(const ljmd_box *box, double alpha, double rc, int64_t n, const double *x,
+                    const double *q, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                    double *F, double *e_total, int accumulate, void *ws, size_t ws_bytes,
+                    void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (!(alpha > 0.0) || !isfinite(alpha)) return set_error(LJMD_EINVAL, "alpha = %g must be > 0", alpha);
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (accumulate != 0 && accumulate != 1)
+    return set_error(LJMD_EINVAL, "accumulate = %d must be 0 or 1", accumulate);
+  if (n > 0 && (!x || !q || !nbr || !nnbr || !F))
+    return set_error(LJMD_EINVAL, "x/q/nbr/nnbr/F is NULL");
+  LJMD_TRY(check_ws(ws, ws_bytes, ewald_real_workspace(n)));
+  if (((uintptr_t)ws & 31u) != 0) return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
+  return launch_ewald_real(make_box(box), alpha, rc, n, x, q, nbr, nnbr, maxn, F, e_total,
+                           accumulate, ws, (hipStream_t)stream);
+}
+
+int ljmd_spme_recip(const ljmd_box *box, double alpha, int32_t order, const int32_t K[3],
+                    int64_t n, const double *x, const double *q, double *F, double *e_total,
+                    int accumulate, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_n(n));
+  if (!(alpha > 0.0) || !isfinite(alpha)) return set_error(LJMD_EINVAL, "alpha = %g must be > 0", alpha);
+  if (order != 4 && order != 6 && order != 8)
+    return set_error(LJMD_EINVAL, "order = %d must be 4, 6 or 8", order);
+  if (!K) return set_error(LJMD_EINVAL, "K is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (K[d] < 8 || K[d] > LJMD_SPME_MAX_GRID || (K[d] & (K[d] - 1)) != 0)
+      return set_error(LJMD_EINVAL, "K[%d] = %d must be a power of two in [8, %d]", d, K[d],
+                       LJMD_SPME_MAX_GRID);
+  if (accumulate != 0 && accumulate != 1)
+    return set_error(LJMD_EINVAL, "accumulate = %d must be 0 or 1", accumulate);
+  if (n > 0 && (!x || !q || !F)) return set_error(LJMD_EINVAL, "x/q/F is NULL");
+  const int64_t npts = (int64_t)K[0] * K[1] * K[2];
+  LJMD_TRY(check_ws(ws, ws_bytes, spme_workspace(n, npts)));
+  if (((uintptr_t)ws & 31u) != 0) return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
+  return launch_spme_recip(make_box(box), alpha, order, K, n, x, q, F, e_total, accumulate, ws,
+                           (hipStream_t)stream);
 }
 
 int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,

@@ -1,0 +1,527 @@
+// Smooth particle-mesh Ewald for point charges, gfx950.  Paper: CabanaMD's
+// long-range path -- real-space energies and forces through the neighbor
+// parallel loops, and for reciprocal space spline spreading of charge onto a
+// uniform grid, 3-D FFTs and a gradient gather back to the particles
+// (CabanaMD subsection; Cabana "Long Range Solvers", "Particle-Grid
+// Interpolation").  The paper prints no equation; the method is SPME as
+// defined by Essmann et al. (1995, J. Chem. Phys. 103, 8577), Gaussian units:
+//
+//   real space:  E_dir = 1/2 sum_i sum_{j, r < rc} q_i q_j erfc(alpha r)/r
+//                F_i   = sum_j q_i q_j [erfc(alpha r)/r + 2 alpha/sqrt(pi) e^{-alpha^2 r^2}] d_ij / r^2
+//   reciprocal:  u_a = K_a x_a / L_a; cardinal B-splines M_n of even order n
+//                Q(k) = sum_i q_i prod_a M_n(u_ai - k_a)   (k_a = floor(u_ai) - j mod K_a)
+//                E_rec = 1/2 sum_m B(m) C(m) |F(Q)(m)|^2,
+//                B = prod_a |sum_{k<n-1} M_n(k+1) e^{2 pi i m_a k/K_a}|^-2,
+//                C = e^{-pi^2 |m'|^2/alpha^2} / (pi V |m'|^2), C(0) = 0
+//                phi = unnormalised inverse transform of B C F(Q);
+//                F_i = -q_i sum_k grad_i[prod_a M_n(u_ai - k_a)] phi(k)
+//   self:        E_self = -alpha/sqrt(pi) sum_i q_i^2
+//
+// Kernels: the real-space pair loop walks the tiled full list with two lanes
+// per particle over packed (x, y, z, q) records (the SPH and LJ traversal);
+// charge spreading is one thread per particle with FP64 hardware atomics on
+// the grid; each 3-D transform is three passes of radix-2 FFTs over rows
+// staged in LDS (rows along y and z are loaded with consecutive x across
+// lanes, so every pass reads and writes whole cache lines); the influence
+// function B C is applied in k-space with the energy summed per block in a
+// fixed order; the gather is one thread per particle.
+#include "common.h"
+
+namespace ljmd {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxOrder = 8;
+constexpr int kMaxGrid = 256;  // points per edge
+constexpr int kThreads = 256;
+constexpr int kEwAtoms = 256;  // real space: particles per block
+constexpr int kEwTeam = 2;
+constexpr int kEwThreads = kEwAtoms * kEwTeam;
+constexpr int kEwUnroll = 6;
+
+// ------------------------------------------------------------ real space --
+
+struct RealArgs {
+  BoxK b;
+  double alpha, a2, c2a;  // alpha, alpha^2, 2 alpha / sqrt(pi)
+  double rc2, margin;
+  int32_t n;
+  const int32_t *nbr;
+  const int32_t *nnbr;
+  int32_t maxn;
+  const double4 *xq;  // packed (x, y, z, q)
+  double *F;
+  int accumulate;
+  double *partial;  // per-block E_dir, or null
+};
+
+__global__ __launch_bounds__(kThreads) void k_pack_xq(int32_t n, const double *x, const double *q,
+                                                      double4 *xq) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  xq[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], q[i]);
+}
+
+template <bool WIDE>
+__device__ __forceinline__ const double4 *xq_of(const double4 *p, int32_t j) {
+  if constexpr (WIDE)
+    return p + j;
+  else
+    return (const double4 *)((const char *)p + ((uint32_t)j << 5));
+}
+
+// One pair: adds q_j-weighted force scalar times d and the energy kernel.
+template <bool WRAP>
+__device__ __forceinline__ void real_pair(const RealArgs &a, const double4 &me, const double4 &o,
+                                          bool ok, double &fx, double &fy, double &fz,
+                                          double &e) {
+  double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+  if constexpr (WRAP) {
+    dx = min_image(dx, a.b.L[0], a.b.invL[0]);
+    dy = min_image(dy, a.b.L[1], a.b.invL[1]);
+    dz = min_image(dz, a.b.L[2], a.b.invL[2]);
+  }
+  const double r2 = dist2(dx, dy, dz);
+  const bool in = ok && r2 < a.rc2;
+  const double rr2 = in ? r2 : 1.0;  // keeps padding and far pairs finite
+  const double r = __builtin_sqrt(rr2);
+  const double ir = recip64(r);
+  const double er = erfc(a.alpha * r) * ir;
+  const double s = (er + a.c2a * exp(-a.a2 * rr2)) * (ir * ir);
+  const double qs = in ? o.w * s : 0.0;
+  fx = __builtin_fma(qs, dx, fx);
+  fy = __builtin_fma(qs, dy, fy);
+  fz = __builtin_fma(qs, dz, fz);
+  e += in ? o.w * er : 0.0;
+}
+
+template <bool WRAP, bool WIDE>
+__device__ __forceinline__ void real_row(const RealArgs &a, const int32_t *row, int32_t cnt,
+                                         const double4 &me, double &fx, double &fy, double &fz,
+                                         double &e) {
+  constexpr int U = kEwUnroll;
+  constexpr int kStep = kEwTeam * kWave;
+  const int32_t whole = cnt - cnt % U;
+  int32_t k = 0;
+  for (; k < whole; k += U, row += U * kStep) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = row[u * kStep];
+    double4 o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) o[u] = *xq_of<WIDE>(a.xq, j[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, me, o[u], true, fx, fy, fz, e);
+  }
+  if (k < cnt) {
+    int32_t j[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok[u] = k + u < cnt;
+      j[u] = row[(ok[u] ? u : 0) * kStep];
+    }
+    double4 o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      o[u] = me;
+      if (ok[u]) o[u] = *xq_of<WIDE>(a.xq, j[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, me, o[u], ok[u], fx, fy, fz, e);
+  }
+}
+
+template <bool WIDE, bool EV>
+__global__ __launch_bounds__(kEwThreads) void k_ewald_real(RealArgs a) {
+  __shared__ double red[kEwThreads / kWave];
+  const int t = (int)threadIdx.x % kEwTeam;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kEwAtoms + (int)threadIdx.x / kEwTeam;
+  const bool live = i < a.n;
+  double4 me = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (live) me = a.xq[i];
+  const double m = a.margin;
+  const bool inside = !live || (me.x >= m && me.x <= a.b.L[0] - m && me.y >= m &&
+                                me.y <= a.b.L[1] - m && me.z >= m && me.z <= a.b.L[2] - m);
+  const bool interior = __ballot(!inside) == 0;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  if (live) {
+    const int32_t ctot = a.nnbr[i];
+    const int32_t cnt = ctot > t ? (ctot - t + kEwTeam - 1) / kEwTeam : 0;
+    const int32_t *row =
+        a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
+    if (interior)
+      real_row<false, WIDE>(a, row, cnt, me, fx, fy, fz, e);
+    else
+      real_row<true, WIDE>(a, row, cnt, me, fx, fy, fz, e);
+  }
+  fx += __shfl_xor(fx, 1, kWave);
+  fy += __shfl_xor(fy, 1, kWave);
+  fz += __shfl_xor(fz, 1, kWave);
+  if (live && t == 0) {
+    double *F = a.F + 3 * (int64_t)i;
+    const double q = me.w;
+    if (a.accumulate) {
+      F[0] += q * fx;
+      F[1] += q * fy;
+      F[2] += q * fz;
+    } else {
+      F[0] = q * fx;
+      F[1] = q * fy;
+      F[2] = q * fz;
+    }
+  }
+  if constexpr (EV) {
+    double v[1] = {live ? 0.5 * me.w * e : 0.0};  // per lane: the team's lanes add up
+    block_sum<kEwThreads / kWave, 1>(v, red, a.partial + blockIdx.x);
+  }
+}
+
+// ------------------------------------------------------------- B-splines --
+
+// M_n(w + j) for j = 0..n-1 (w in [0, 1)) by the recursion
+//   M_k(v) = (v M_{k-1}(v) + (k - v) M_{k-1}(v - 1)) / (k - 1),  M_2(w) = w, M_2(w+1) = 1 - w;
+// dm receives dM_n(w + j)/dv = M_{n-1}(w + j) - M_{n-1}(w + j - 1) when requested.
+template <int N, bool DERIV>
+__device__ __forceinline__ void spline_weights(double w, double (&m)[N], double (&dm)[N]) {
+  double a[N];
+  a[0] = w;
+  a[1] = 1.0 - w;
+#pragma unroll
+  for (int j = 2; j < N; ++j) a[j] = 0.0;
+#pragma unroll
+  for (int k = 3; k <= N; ++k) {
+    if (DERIV && k == N) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) dm[j] = a[j] - (j > 0 ? a[j - 1] : 0.0);
+    }
+    const double inv = 1.0 / (k - 1);
+#pragma unroll
+    for (int j = k - 1; j >= 0; --j) {
+      const double v = w + j;
+      const double lo = j > 0 ? a[j - 1] : 0.0;
+      a[j] = (v * a[j] + (k - v) * lo) * inv;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) m[j] = a[j];
+}
+
+struct RecArgs {
+  BoxK b;
+  int32_t K[3];
+  double scale[3];  // K_a / L_a
+  double alpha;
+  int32_t n;
+  const double *x;
+  const double *q;
+  double2 *grid;       // [K2][K1][K0] complex, x fastest
+  double *bmod;        // |b_a(m)|^2 tables at bmod + a * kMaxGrid
+  double *partial;     // influence blocks, then gather blocks
+  double *F;
+  int accumulate;
+};
+
+__device__ __forceinline__ int wrapi(int k, int K) {
+  k %= K;
+  return k < 0 ? k + K : k;
+}
+
+// |b_a(m)|^2 = |sum_{k=0}^{n-2} M_n(k+1) e^{2 pi i m k / K_a}|^-2 for every axis a, m < K_a.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_bmod(RecArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ax = t / kMaxGrid, m = t % kMaxGrid;
+  if (ax >= 3 || m >= a.K[ax]) return;
+  double mk[N], dk[N];
+  spline_weights<N, false>(0.0, mk, dk);  // mk[j] = M_n(j): M_n(k+1) = mk[k+1]
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k <= N - 2; ++k) {
+    double s, c;
+    sincospi(2.0 * (double)((int64_t)m * k % a.K[ax]) / a.K[ax], &s, &c);
+    re += mk[k + 1] * c;
+    im += mk[k + 1] * s;
+  }
+  a.bmod[ax * kMaxGrid + m] = 1.0 / (re * re + im * im);
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_grid(double2 *g, int64_t npts) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < npts) g[i] = make_double2(0.0, 0.0);
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_spread(RecArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double w[3][N], dw[N];
+  int base[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double u = a.x[3 * i + d] * a.scale[d];
+    const double fl = floor(u);
+    base[d] = (int)fl;
+    spline_weights<N, false>(u - fl, w[d], dw);
+  }
+  const double qi = a.q[i];
+  for (int jz = 0; jz < N; ++jz) {
+    const int kz = wrapi(base[2] - jz, a.K[2]);
+    for (int jy = 0; jy < N; ++jy) {
+      const int ky = wrapi(base[1] - jy, a.K[1]);
+      const double wyz = qi * w[2][jz] * w[1][jy];
+      double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
+#pragma unroll
+      for (int jx = 0; jx < N; ++jx)
+        unsafeAtomicAdd(&line[wrapi(base[0] - jx, a.K[0])].x, wyz * w[0][jx]);
+    }
+  }
+}
+
+// Radix-2 transform of rows of length NP along one axis, R rows per block
+// staged in LDS: bit-reversed load, log2(NP) butterfly stages, natural-order
+// store.  sign = -1: sum_k v_k e^{-2 pi i m k / NP}; +1: the unnormalised inverse.
+// rows per block: 1024 points, at most 64 rows (a power of two that divides the
+// row count, which is the product of two edges of at least 8 points each)
+template <int NP>
+constexpr int fft_rows() {
+  return 1024 / NP < 64 ? 1024 / NP : 64;
+}
+
+template <int NP>
+__global__ __launch_bounds__(kThreads) void k_fft(double2 *g, int axis, int K0, int K1,
+                                                  double sign) {
+  constexpr int R = fft_rows<NP>();
+  constexpr int LOG = __builtin_ctz(NP);
+  __shared__ double2 buf[R * NP];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int64_t plane = (int64_t)K0 * K1;
+  auto addr = [&](int m, int k) -> int64_t {
+    const int64_t r = r0 + m;
+    if (axis == 0) return r * NP + k;
+    if (axis == 1) return (r % K0) + (r / K0) * plane + (int64_t)k * K0;
+    return r + (int64_t)k * plane;
+  };
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = axis == 0 ? idx / NP : idx % R;
+    const int k = axis == 0 ? idx % NP : idx / R;
+    const int kr = (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - LOG));
+    buf[m * NP + kr] = g[addr(m, k)];
+  }
+  __syncthreads();
+  for (int h = 1; h < NP; h <<= 1) {
+    for (int b = threadIdx.x; b < R * NP / 2; b += kThreads) {
+      const int m = b / (NP / 2), bb = b % (NP / 2);
+      const int pos = bb % h, grp = bb / h;
+      const int i0 = m * NP + grp * 2 * h + pos, i1 = i0 + h;
+      double s, c;
+      sincospi(sign * (double)pos / (double)h, &s, &c);
+      const double2 u = buf[i0], v = buf[i1];
+      const double tr = c * v.x - s * v.y, ti = c * v.y + s * v.x;
+      buf[i0] = make_double2(u.x + tr, u.y + ti);
+      buf[i1] = make_double2(u.x - tr, u.y - ti);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = axis == 0 ? idx / NP : idx % R;
+    const int k = axis == 0 ? idx % NP : idx / R;
+    g[addr(m, k)] = buf[m * NP + k];
+  }
+}
+
+// F(Q)(m) *= B(m) C(m); per block 1/2 sum B C |F(Q)|^2 (fixed order)
+__global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
+  __shared__ double red[kThreads / kWave];
+  const int64_t npts = (int64_t)a.K[0] * a.K[1] * a.K[2];
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (p < npts) {
+    const int m0 = (int)(p % a.K[0]);
+    const int m1 = (int)((p / a.K[0]) % a.K[1]);
+    const int m2 = (int)(p / ((int64_t)a.K[0] * a.K[1]));
+    const double f0 = (m0 <= a.K[0] / 2 ? m0 : m0 - a.K[0]) * a.b.invL[0];
+    const double f1 = (m1 <= a.K[1] / 2 ? m1 : m1 - a.K[1]) * a.b.invL[1];
+    const double f2 = (m2 <= a.K[2] / 2 ? m2 : m2 - a.K[2]) * a.b.invL[2];
+    const double msq = (f0 * f0 + f1 * f1) + f2 * f2;
+    double G = 0.0;
+    if (p != 0) {
+      const double V = a.b.L[0] * a.b.L[1] * a.b.L[2];
+      const double C = exp(-kPi * kPi * msq / (a.alpha * a.alpha)) / (kPi * V * msq);
+      G = C * a.bmod[m0] * a.bmod[kMaxGrid + m1] * a.bmod[2 * kMaxGrid + m2];
+    }
+    const double2 z = a.grid[p];
+    v[0] = 0.5 * G * (z.x * z.x + z.y * z.y);
+    a.grid[p] = make_double2(G * z.x, G * z.y);
+  }
+  block_sum<kThreads / kWave, 1>(v, red, a.partial + blockIdx.x);
+}
+
+// F_i = -q_i grad sum_k theta_i(k) phi(k); per block the self energy -alpha/sqrt(pi) q_i^2
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_gather(RecArgs a, double *self_partial) {
+  __shared__ double red[kThreads / kWave];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (i < a.n) {
+    double w[3][N], dw[3][N];
+    int base[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = a.x[3 * i + d] * a.scale[d];
+      const double fl = floor(u);
+      base[d] = (int)fl;
+      spline_weights<N, true>(u - fl, w[d], dw[d]);
+    }
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int jz = 0; jz < N; ++jz) {
+      const int kz = wrapi(base[2] - jz, a.K[2]);
+      for (int jy = 0; jy < N; ++jy) {
+        const int ky = wrapi(base[1] - jy, a.K[1]);
+        const double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
+        double sx = 0.0, sdx = 0.0;
+#pragma unroll
+        for (int jx = 0; jx < N; ++jx) {
+          const double ph = line[wrapi(base[0] - jx, a.K[0])].x;
+          sx = __builtin_fma(w[0][jx], ph, sx);
+          sdx = __builtin_fma(dw[0][jx], ph, sdx);
+        }
+        g0 = __builtin_fma(sdx * w[1][jy], w[2][jz], g0);
+        g1 = __builtin_fma(sx * dw[1][jy], w[2][jz], g1);
+        g2 = __builtin_fma(sx * w[1][jy], dw[2][jz], g2);
+      }
+    }
+    const double qi = a.q[i];
+    double *F = a.F + 3 * i;
+    const double f0 = -qi * g0 * a.scale[0], f1 = -qi * g1 * a.scale[1],
+                 f2 = -qi * g2 * a.scale[2];
+    if (a.accumulate) {
+      F[0] += f0;
+      F[1] += f1;
+      F[2] += f2;
+    } else {
+      F[0] = f0;
+      F[1] = f1;
+      F[2] = f2;
+    }
+    v[0] = -a.alpha / __builtin_sqrt(kPi) * qi * qi;
+  }
+  if (self_partial) block_sum<kThreads / kWave, 1>(v, red, self_partial + blockIdx.x);
+}
+
+template <int NP>
+void fft_pass(double2 *g, int axis, const int32_t K[3], double sign, hipStream_t st) {
+  constexpr int R = fft_rows<NP>();
+  const int64_t rows = (int64_t)K[0] * K[1] * K[2] / NP;
+  k_fft<NP><<<(unsigned)(rows / R), kThreads, 0, st>>>(g, axis, K[0], K[1], sign);
+}
+
+void fft_axis(double2 *g, int axis, const int32_t K[3], double sign, hipStream_t st) {
+  switch (K[axis]) {
+    case 8: fft_pass<8>(g, axis, K, sign, st); break;
+    case 16: fft_pass<16>(g, axis, K, sign, st); break;
+    case 32: fft_pass<32>(g, axis, K, sign, st); break;
+    case 64: fft_pass<64>(g, axis, K, sign, st); break;
+    case 128: fft_pass<128>(g, axis, K, sign, st); break;
+    default: fft_pass<256>(g, axis, K, sign, st); break;
+  }
+}
+
+int64_t grid_points(const int32_t K[3]) { return (int64_t)K[0] * K[1] * K[2]; }
+unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per > 0 ? (n + per - 1) / per : 1); }
+
+template <int N>
+void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
+  const int64_t npts = grid_points(a.K);
+  k_bmod<N><<<blocks_of(3 * kMaxGrid, kThreads), kThreads, 0, st>>>(a);
+  k_zero_grid<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a.grid, npts);
+  if (a.n > 0) k_spread<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a);
+  for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, -1.0, st);
+  k_influence<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a);
+  for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, 1.0, st);
+  if (a.n > 0) k_gather<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a, self_partial);
+}
+
+}  // namespace
+
+size_t ewald_real_workspace(int64_t n) {
+  return (size_t)(n > 0 ? n : 0) * sizeof(double4) +
+         (size_t)blocks_of(n, kEwAtoms) * sizeof(double) + 256;
+}
+
+size_t spme_workspace(int64_t n, int64_t npts) {
+  return (size_t)npts * sizeof(double2) + 3 * kMaxGrid * sizeof(double) +
+         ((size_t)blocks_of(npts, kThreads) + blocks_of(n, kThreads)) * sizeof(double) + 256;
+}
+
+int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const double *x,
+                      const double *q, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
+                      double *F, double *e_total, int accumulate, void *ws, hipStream_t st) {
+  RealArgs a{};
+  a.b = b;
+  a.alpha = alpha;
+  a.a2 = alpha * alpha;
+  a.c2a = 2.0 * alpha / sqrt(kPi);
+  a.rc2 = rc * rc;
+  a.margin = rc;
+  a.n = (int32_t)n;
+  a.nbr = nbr;
+  a.nnbr = nnbr;
+  a.maxn = maxn;
+  a.xq = (const double4 *)ws;
+  a.F = F;
+  a.accumulate = accumulate;
+  const unsigned nblk = blocks_of(n, kEwAtoms);
+  a.partial = (double *)((char *)ws + (size_t)(n > 0 ? n : 0) * sizeof(double4));
+  if (n > 0) {
+    k_pack_xq<<<blocks_of(n, kThreads), kThreads, 0, st>>>((int32_t)n, x, q, (double4 *)ws);
+    const bool wide = n > kNarrowAtoms;
+    if (e_total) {
+      if (wide) k_ewald_real<true, true><<<nblk, kEwThreads, 0, st>>>(a);
+      else k_ewald_real<false, true><<<nblk, kEwThreads, 0, st>>>(a);
+    } else {
+      if (wide) k_ewald_real<true, false><<<nblk, kEwThreads, 0, st>>>(a);
+      else k_ewald_real<false, false><<<nblk, kEwThreads, 0, st>>>(a);
+    }
+  }
+  if (e_total) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 0, 1, 1, a.partial, e_total, 1.0, 0);
+  return check_launch("ljmd_ewald_real");
+}
+
+int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t K[3], int64_t n,
+                      const double *x, const double *q, double *F, double *e_total,
+                      int accumulate, void *ws, hipStream_t st) {
+  RecArgs a{};
+  a.b = b;
+  for (int d = 0; d < 3; ++d) {
+    a.K[d] = K[d];
+    a.scale[d] = (double)K[d] / b.L[d];
+  }
+  a.alpha = alpha;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.q = q;
+  a.F = F;
+  a.accumulate = accumulate;
+  const int64_t npts = grid_points(K);
+  char *p = (char *)ws;
+  a.grid = (double2 *)p;
+  p += (size_t)npts * sizeof(double2);
+  a.bmod = (double *)p;
+  p += 3 * kMaxGrid * sizeof(double);
+  a.partial = (double *)p;
+  const unsigned ninf = blocks_of(npts, kThreads);
+  const unsigned ngat = blocks_of(n, kThreads);
+  double *self_partial = n > 0 ? a.partial + ninf : nullptr;
+  switch (order) {
+    case 4: launch_rec_order<4>(a, self_partial, st); break;
+    case 6: launch_rec_order<6>(a, self_partial, st); break;
+    default: launch_rec_order<8>(a, self_partial, st); break;
+  }
+  if (e_total)
+    k_colsum<256><<<1, 256, 0, st>>>((int64_t)ninf + (n > 0 ? ngat : 0), 1, 1, a.partial, e_total,
+                                     1.0, 0);
+  return check_launch("ljmd_spme_recip");
+}
+
+}  // namespace ljmd

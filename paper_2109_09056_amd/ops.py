@@ -16,8 +16,8 @@ from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
                    MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
-                   OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_SPH, TILE, LjmdError,
-                   make_box)
+                   OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_SPH, OP_SPME,
+                   SPME_MAX_GRID, TILE, LjmdError, make_box)
 
 
 def _ptr(t):
@@ -406,3 +406,45 @@ def sph_accel(L, h, mass, c0, rho0, x, rho, nbr, nnbr, maxn, acc=None, ws=None):
         _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(acc), _ptr(ws), need, _stream(dev)),
         "ljmd_sph_accel")
     return acc
+
+
+def ewald_real(L, alpha, rc, x, q, nbr, nnbr, maxn, F=None, e_total=None, want_energy=False,
+               accumulate=False, ws=None):
+    """Ewald direct-space forces (and E_dir) over a FULL list with rlist >= rc."""
+    n, dev = _sph_list(x, nbr, nnbr, maxn)
+    _need(q, "q", torch.float64, (n,), dev)
+    if F is None:
+        F = torch.zeros_like(x)
+    if want_energy and e_total is None:
+        e_total = torch.empty(1, dtype=torch.float64, device=dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_total, "e_total", torch.float64, (1,), dev)
+    ws, need = _ws(OP_EWALD_REAL, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_ewald_real(
+        ctypes.byref(b), float(alpha), float(rc), n, _ptr(x), _ptr(q), _ptr(nbr), _ptr(nnbr),
+        int(maxn), _ptr(F), _ptr(e_total), int(bool(accumulate)), _ptr(ws), need, _stream(dev)),
+        "ljmd_ewald_real")
+    return F, e_total
+
+
+def spme_recip(L, alpha, order, K, x, q, F=None, e_total=None, want_energy=False,
+               accumulate=False, ws=None):
+    """SPME reciprocal-space forces (and E_rec + E_self) on a K[0] x K[1] x K[2] grid."""
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(q, "q", torch.float64, (n,), dev)
+    if F is None:
+        F = torch.zeros_like(x)
+    if want_energy and e_total is None:
+        e_total = torch.empty(1, dtype=torch.float64, device=dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_total, "e_total", torch.float64, (1,), dev)
+    Kc = (ctypes.c_int32 * 3)(*[int(k) for k in K])
+    ws, need = _ws(OP_SPME, n, dev, ncells=int(K[0]) * int(K[1]) * int(K[2]), ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_spme_recip(
+        ctypes.byref(b), float(alpha), int(order), Kc, n, _ptr(x), _ptr(q), _ptr(F),
+        _ptr(e_total), int(bool(accumulate)), _ptr(ws), need, _stream(dev)), "ljmd_spme_recip")
+    return F, e_total

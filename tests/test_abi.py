@@ -49,6 +49,8 @@ def test_workspace_sizes(lib):
     assert W(lib.OP_FORCES, 500000, 0, 1) >= 8 * 7 * (500000 // 256)
     assert W(lib.OP_BACKWARD, 1000, 0, 2) >= W(lib.OP_BACKWARD, 1000, 0, 1)
     assert W(lib.OP_SPH, 1000, 0, 1) >= 32 * 1000
+    assert W(lib.OP_EWALD_REAL, 1000, 0, 1) >= 32 * 1000
+    assert W(lib.OP_SPME, 1000, 64 ** 3, 1) >= 16 * 64 ** 3
     assert W(99, 10, 10, 1) == 0
 
 
@@ -157,6 +159,28 @@ def test_validation_rejects_bad_arguments(lib):
     assert call(lib, "ljmd_sph_accel", bb, 1.3, 1.0, 10.0, 1.0, 10, fake, fake, fake, fake, 8,
                 fake, ctypes.c_void_p(4096 + 16), 1 << 20, None) == lib.EINVAL
     assert b"aligned" in lib.load().ljmd_last_error()
+    # Ewald real space: alpha <= 0, rc too large, bad accumulate, missing q, no workspace,
+    # misaligned workspace
+    ea = lambda alpha, rc, qq, acc, ws, wsb: (bb, alpha, rc, 10, fake, qq, fake, fake, 8, fake,
+                                              None, acc, ws, wsb, None)
+    big = 1 << 20
+    assert call(lib, "ljmd_ewald_real", *ea(0.0, 2.5, fake, 0, fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_ewald_real", *ea(1.2, 5.1, fake, 0, fake, big)) == lib.EBOX
+    assert call(lib, "ljmd_ewald_real", *ea(1.2, 2.5, fake, 2, fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_ewald_real", *ea(1.2, 2.5, None, 0, fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_ewald_real", *ea(1.2, 2.5, fake, 0, None, 0)) == lib.EWORKSPACE
+    assert call(lib, "ljmd_ewald_real", *ea(1.2, 2.5, fake, 0, ctypes.c_void_p(4096 + 8),
+                                            big)) == lib.EINVAL
+    # SPME: bad order, grid not a power of two / out of range, missing K, no workspace
+    K = lambda a, b, c: (ctypes.c_int32 * 3)(a, b, c)
+    sa = lambda order, k, ws, wsb: (bb, 1.2, order, k, 10, fake, fake, fake, None, 0, ws, wsb,
+                                    None)
+    assert call(lib, "ljmd_spme_recip", *sa(5, K(16, 16, 16), fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_spme_recip", *sa(4, K(16, 24, 16), fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_spme_recip", *sa(4, K(4, 16, 16), fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_spme_recip", *sa(4, K(16, 16, 512), fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_spme_recip", *sa(4, None, fake, big)) == lib.EINVAL
+    assert call(lib, "ljmd_spme_recip", *sa(4, K(16, 16, 16), None, 0)) == lib.EWORKSPACE
     assert call(lib, "ljmd_scatter_rows", 10, 0, fake, fake, fake, None) == lib.EINVAL
     assert call(lib, "ljmd_gather_rows", -1, 3, fake, fake, fake, None) == lib.EINVAL
     assert call(lib, "ljmd_traj_loss", bb, 10, fake, fake, fake, None, fake, 1 << 20,
