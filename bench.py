@@ -53,6 +53,8 @@ def parse():
                     help="target length of the oracle's CPU sample")
     ap.add_argument("--sph-only", action="store_true",
                     help="run only the SPH leg (512,000 particles) and print its JSON object")
+    ap.add_argument("--spme-only", action="store_true",
+                    help="run only the SPME leg (500,000 charges) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (x5), to calibrate HBM "
                          "byte counters")
@@ -302,6 +304,51 @@ def sph_bench(dev, steps=300, warmup=50, reps=50):
             "accel_frac": round(ba / (ta * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def spme_bench(dev, reps=30):
+    """Long-range electrostatics on the 500,000-atom liquid with unit charges (half +1,
+    half -1): Ewald real space over the MD list (rc 2.5, alpha 1.2) and the SPME
+    reciprocal part (order-4 B-splines, 128^3 grid), each timed alone with HIP events.
+    Algorithmic bytes: real space per particle 4 nbar + 4 + 32 (own record) + 24 (F)
+    + 56 (packing x, q into records); reciprocal per grid point 16 (zero) + 6 x 32
+    (three FFT passes each way, read + write) + 32 (influence), per particle 32 (x, q)
+    + 24 (F) + 2 x 64 x 8 (spread and gather of n^3 = 64 points; atomics counted once)."""
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj500k"]
+    x = torch.as_tensor(li.positions(w), dtype=torch.float64, device=dev)
+    q = torch.as_tensor(li.charges(w), dtype=torch.float64, device=dev)
+    L, K, order, alpha = w.box, li.ewald_grid(w.box), li.EWALD_ORDER, li.EWALD_ALPHA
+    xs, _, _, ids, cs = ops.bin(L, w.rlist, x)
+    qs = ops.gather_rows(ids, q)
+    nl = md.NeighborList(L, w.rlist, ops.FULL, device=dev).build(xs, cs)
+    F = torch.zeros_like(xs)
+    E = torch.zeros(2, dtype=torch.float64, device=dev)
+    wr = torch.empty(ops.workspace_bytes(ops.OP_EWALD_REAL, w.natoms), dtype=torch.uint8,
+                     device=dev)
+    wk = torch.empty(ops.workspace_bytes(ops.OP_SPME, w.natoms, ncells=K[0] * K[1] * K[2]),
+                     dtype=torch.uint8, device=dev)
+    real = lambda: ops.ewald_real(L, alpha, w.rc, xs, qs, nl.nbr, nl.nnbr, nl.maxn, F=F,
+                                  e_total=E[:1], ws=wr)
+    recip = lambda: ops.spme_recip(L, alpha, order, K, xs, qs, F=F, e_total=E[1:],
+                                   accumulate=True, ws=wk)
+    tr = event_time(real, reps)
+    tk = event_time(recip, reps)
+    tb = event_time(lambda: (real(), recip()), reps)
+    n = w.natoms
+    nb = float(nl.nnbr.double().mean().item())
+    npts = K[0] * K[1] * K[2]
+    br = n * (4.0 * nb + 116)
+    bk = npts * (16 + 6 * 32 + 32) + n * (56 + 2 * 64 * 8)
+    return {"natoms": n, "grid": list(K), "order": order, "alpha": alpha, "rc": w.rc,
+            "real_us": round(tr * 1e3, 2), "recip_us": round(tk * 1e3, 2),
+            "both_us": round(tb * 1e3, 2),
+            "value": round(n / (tb * 1e-3), 1), "unit": "atom-evaluations/s",
+            "real_GBps": round(br / (tr * 1e-3) / 1e9, 1),
+            "recip_GBps": round(bk / (tk * 1e-3) / 1e9, 1),
+            "energy": [float(v) for v in E.cpu()]}
+
+
 def cpu_baseline(w, s, target_s):
     """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input."""
     import numpy as np
@@ -341,6 +388,9 @@ def main():
     _lib.load()
     if args.sph_only:
         print(json.dumps({"sph_512k": sph_bench(dev)}), flush=True)
+        return
+    if args.spme_only:
+        print(json.dumps({"spme_500k": spme_bench(dev)}), flush=True)
         return
     w = li.WORKLOADS[args.workload]
     s = li.make_system(w)
@@ -405,6 +455,8 @@ def main():
         del sim2, s2
         line["sph_512k"] = sph_bench(dev)
         log(f"[bench] SPH 512k: {line['sph_512k']}")
+        line["spme_500k"] = spme_bench(dev)
+        log(f"[bench] SPME 500k: {line['spme_500k']}")
         line["shard_share_2x2x2"] = shard_share(dev)
         log(f"[bench] one 2x2x2 shard: {line['shard_share_2x2x2']}")
         log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")

@@ -251,30 +251,89 @@ __global__ __launch_bounds__(kThreads) void k_zero_grid(double2 *g, int64_t npts
   if (i < npts) g[i] = make_double2(0.0, 0.0);
 }
 
+// Charge spreading, one wavefront of 64 consecutive (cell-sorted, hence
+// nearby) particles per block.  The wavefront first adds its n^3 weights per
+// particle into a private box of grid points in LDS (LDS atomics), then adds
+// every non-zero point of that box to the grid with one global FP64 atomic:
+// ~4x fewer global atomics than adding each weight directly, which is what
+// bounds this kernel.  Per axis the box is taken in whichever of two cyclic
+// frames (indices as they are, or shifted by K/2) gives the smaller extent,
+// so groups that straddle a periodic face stay compact.  A group whose box
+// exceeds the LDS capacity adds its weights straight to the grid.
+constexpr int kSpreadCap = 2048;  // grid points (doubles) in the LDS box
+
+__device__ __forceinline__ int wave_min_i(int v) { return -wave_max(-v); }
+
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_spread(RecArgs a) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+__global__ __launch_bounds__(kWave) void k_spread(RecArgs a) {
+  __shared__ double box[kSpreadCap];
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  const bool live = i < a.n;
   double w[3][N], dw[N];
-  int base[3];
+  int b[3] = {0, 0, 0};
+  double qi = 0.0;
+  if (live) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = a.x[3 * i + d] * a.scale[d];
+      const double fl = floor(u);
+      b[d] = wrapi((int)fl, a.K[d]);
+      spline_weights<N, false>(u - fl, w[d], dw);
+    }
+    qi = a.q[i];
+  }
+  int lo[3], ext[3], sh[3], sb[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double u = a.x[3 * i + d] * a.scale[d];
-    const double fl = floor(u);
-    base[d] = (int)fl;
-    spline_weights<N, false>(u - fl, w[d], dw);
+    const int K = a.K[d];
+    const int s0 = b[d], s1 = (b[d] + K / 2) % K;
+    const int mn0 = wave_min_i(live ? s0 : 1 << 30), mx0 = wave_max(live ? s0 : -(1 << 30));
+    const int mn1 = wave_min_i(live ? s1 : 1 << 30), mx1 = wave_max(live ? s1 : -(1 << 30));
+    const bool shift = mx1 - mn1 < mx0 - mn0;
+    sh[d] = shift ? K / 2 : 0;
+    lo[d] = shift ? mn1 : mn0;
+    ext[d] = (shift ? mx1 - mn1 : mx0 - mn0) + N;
+    sb[d] = shift ? s1 : s0;
   }
-  const double qi = a.q[i];
-  for (int jz = 0; jz < N; ++jz) {
-    const int kz = wrapi(base[2] - jz, a.K[2]);
-    for (int jy = 0; jy < N; ++jy) {
-      const int ky = wrapi(base[1] - jy, a.K[1]);
-      const double wyz = qi * w[2][jz] * w[1][jy];
-      double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
+  const int64_t vol = (int64_t)ext[0] * ext[1] * ext[2];
+  if (vol > kSpreadCap) {  // wavefront-uniform
+    if (!live) return;
+    for (int jz = 0; jz < N; ++jz) {
+      const int kz = wrapi(b[2] - jz, a.K[2]);
+      for (int jy = 0; jy < N; ++jy) {
+        const int ky = wrapi(b[1] - jy, a.K[1]);
+        const double wyz = qi * w[2][jz] * w[1][jy];
+        double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
 #pragma unroll
-      for (int jx = 0; jx < N; ++jx)
-        unsafeAtomicAdd(&line[wrapi(base[0] - jx, a.K[0])].x, wyz * w[0][jx]);
+        for (int jx = 0; jx < N; ++jx)
+          unsafeAtomicAdd(&line[wrapi(b[0] - jx, a.K[0])].x, wyz * w[0][jx]);
+      }
     }
+    return;
+  }
+  for (int p = lane; p < vol; p += kWave) box[p] = 0.0;
+  __syncthreads();
+  if (live) {
+    const int c0 = sb[0] - lo[0] + N - 1, c1 = sb[1] - lo[1] + N - 1, c2 = sb[2] - lo[2] + N - 1;
+    for (int jz = 0; jz < N; ++jz) {
+      for (int jy = 0; jy < N; ++jy) {
+        const double wyz = qi * w[2][jz] * w[1][jy];
+        double *row = box + ((int64_t)(c2 - jz) * ext[1] + (c1 - jy)) * ext[0] + c0;
+#pragma unroll
+        for (int jx = 0; jx < N; ++jx) unsafeAtomicAdd(row - jx, wyz * w[0][jx]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int p = lane; p < vol; p += kWave) {
+    const double v = box[p];
+    if (v == 0.0) continue;
+    const int l0 = p % ext[0], l1 = (p / ext[0]) % ext[1], l2 = p / (ext[0] * ext[1]);
+    const int k0 = wrapi(lo[0] + l0 - (N - 1) - sh[0], a.K[0]);
+    const int k1 = wrapi(lo[1] + l1 - (N - 1) - sh[1], a.K[1]);
+    const int k2 = wrapi(lo[2] + l2 - (N - 1) - sh[2], a.K[2]);
+    unsafeAtomicAdd(&a.grid[((int64_t)k2 * a.K[1] + k1) * a.K[0] + k0].x, v);
   }
 }
 
@@ -435,7 +494,7 @@ void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
   const int64_t npts = grid_points(a.K);
   k_bmod<N><<<blocks_of(3 * kMaxGrid, kThreads), kThreads, 0, st>>>(a);
   k_zero_grid<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a.grid, npts);
-  if (a.n > 0) k_spread<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a);
+  if (a.n > 0) k_spread<N><<<blocks_of(a.n, kWave), kWave, 0, st>>>(a);
   for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, -1.0, st);
   k_influence<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a);
   for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, 1.0, st);
