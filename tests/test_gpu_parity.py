@@ -449,6 +449,15 @@ def test_wide_indices_17m(dev, orc):
             assert np.linalg.norm(Fs - Fo, axis=1).max() <= MIXED_F_TOL * frms
             assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
         del F, e
+    # Ewald real space on the wide path: unit charges, the same sampled rows against the
+    # oracle's direct sum over all atoms
+    q = li.charges(w)
+    qs = ops.gather_rows(sim.ids, torch.as_tensor(q, dtype=torch.float64, device=dev))
+    Fq, _ = ops.ewald_real(w.box, li.EWALD_ALPHA, w.rc, sim.x, qs, sim.nl.nbr, sim.nl.nnbr,
+                           sim.nl.maxn)
+    _, Fq_o = orc.ewald_direct(x, q, w.box, li.EWALD_ALPHA, w.rc, sel=ids)
+    assert np.abs(Fq[p].cpu().numpy() - Fq_o).max() <= 1e-12 * np.abs(Fq_o).max()
+    del Fq, qs
     # fused step == forces + closing kick + opening kick/drift, bitwise, on the wide path
     v1 = torch.zeros_like(sim.x)
     xn, F1, ev1 = ops.md_step(w.box, ops.MIXED, w.rc, one, one, sim.x, sim.types, sim.nl.nbr,

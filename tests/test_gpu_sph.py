@@ -160,3 +160,35 @@ def test_trajectory_vs_oracle_and_energy(dev, orc):
         Es.append(sum(sim.energy()))
     assert max(abs(e - E0) for e in Es) < 2e-3 * abs(E0)
     assert sim.nl.overflows == 0
+
+
+def test_wide_indices_17m(dev, orc):
+    """17,173,512 particles (258^3): sorted indices above 2^24 take the wide (64-bit)
+    gather addressing in both passes; 12 particles of the top cell layer (sorted last)
+    against the oracle, with the oracle's densities of every particle within 2h."""
+    from paper_2109_09056_amd import sph
+    w = li.SphWorkload("sph17m", 3, cells=258)
+    x = li.sph_positions(w)
+    n, L = x.shape[0], w.box
+    assert n > (1 << 24)
+    sim = sph.SPHSim(L, w.h, mass=w.mass, c0=w.c0, rho0=w.rho0, skin=w.skin, device=dev)
+    sim.load(x)
+    top = np.nonzero(x[:, 2] >= L[2] - 2.0)[0]
+    samp = np.random.default_rng(6).choice(top, 12, replace=False)
+    ids = sim.ids.cpu().numpy()
+    pos = np.empty_like(ids)
+    pos[ids] = np.arange(n)
+    assert (pos[samp] >= (1 << 24)).all()
+    near = []
+    for i in samp:
+        d = x - x[i]
+        d -= L * np.round(d / L)
+        near.append(np.nonzero((d * d).sum(-1) < (2 * w.h) ** 2)[0])
+    need = np.union1d(np.concatenate(near), samp)
+    rho_full = np.full(n, np.nan)
+    rho_full[need] = orc.sph_density(x, L, w.h, w.mass, sel=need)
+    a_o = orc.sph_accel(x, L, w.h, w.mass, w.c0, w.rho0, rho_full, sel=samp)
+    rho_g = sim.rho.cpu().numpy()[pos[need]]
+    a_g = sim.acc.cpu().numpy()[pos[samp]]
+    assert np.abs(rho_g - rho_full[need]).max() <= TOL * np.abs(rho_full[need]).max()
+    assert np.abs(a_g - a_o).max() <= TOL * np.abs(a_o).max()
