@@ -18,7 +18,8 @@
 //   self:        E_self = -alpha/sqrt(pi) sum_i q_i^2
 //
 // Kernels: the real-space pair loop walks the tiled full list with two lanes
-// per particle over packed (x, y, z, q) records (the SPH and LJ traversal);
+// per particle over packed (x, y, z, q) records (the SPH and LJ traversal),
+// with erfc taken as e^{-x^2} times a tabulated polynomial for erfcx;
 // charge spreading is one thread per particle with FP64 hardware atomics on
 // the grid; each 3-D transform is three passes of radix-2 FFTs over rows
 // staged in LDS (rows along y and z are loaded with consecutive x across
@@ -39,6 +40,13 @@ constexpr int kEwAtoms = 256;  // real space: particles per block
 constexpr int kEwTeam = 2;
 constexpr int kEwThreads = kEwAtoms * kEwTeam;
 constexpr int kEwUnroll = 6;
+// erfc(x) = e^{-x^2} erfcx(x) on [0, alpha rc]: erfcx by degree-10 Taylor polynomials
+// about the centres of 32 equal intervals (relative error ~1e-15); e^{-x^2} is
+// needed for the force anyway, so a pair costs ten FMAs instead of a library erfc.
+constexpr int kErfcIntervals = 32;
+constexpr int kErfcDegree = 10;
+constexpr int kErfcStride = 12;  // coefficients per interval, padded
+constexpr int kErfcTable = kErfcIntervals * kErfcStride;
 
 // ------------------------------------------------------------ real space --
 
@@ -54,10 +62,33 @@ struct RealArgs {
   double *F;
   int accumulate;
   double *partial;  // per-block E_dir, or null
+  const double *erfcx_tab;  // [kErfcIntervals][kErfcStride] Taylor coefficients
+  double inv_dx, half_dx;   // intervals of width dx = alpha rc / kErfcIntervals
 };
 
+// Packs (x, y, z, q) records; block 0 also writes the erfcx table: about each
+// interval centre c, a_n = erfcx^(n)(c) / n! from erfcx(c) = e^{c^2} erfc(c) and
+// the recurrence y' = 2 x y - 2/sqrt(pi), y^(n+1) = 2 x y^(n) + 2 n y^(n-1).
 __global__ __launch_bounds__(kThreads) void k_pack_xq(int32_t n, const double *x, const double *q,
-                                                      double4 *xq) {
+                                                      double4 *xq, double half_dx,
+                                                      double *erfcx_tab) {
+  if (blockIdx.x == 0 && threadIdx.x < kErfcIntervals) {
+    const double c = (2 * threadIdx.x + 1) * half_dx;
+    double *a = erfcx_tab + threadIdx.x * kErfcStride;
+    double ym1 = exp(c * c) * erfc(c);
+    double y = 2.0 * c * ym1 - 2.0 / sqrt(kPi);
+    double fact = 1.0;
+    a[0] = ym1;
+    a[1] = y;
+    for (int k = 1; k < kErfcDegree; ++k) {
+      const double yn = 2.0 * c * y + 2.0 * k * ym1;
+      fact *= (k + 1);
+      a[k + 1] = yn / fact;
+      ym1 = y;
+      y = yn;
+    }
+    for (int k = kErfcDegree + 1; k < kErfcStride; ++k) a[k] = 0.0;
+  }
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   xq[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], q[i]);
@@ -73,9 +104,9 @@ __device__ __forceinline__ const double4 *xq_of(const double4 *p, int32_t j) {
 
 // One pair: adds q_j-weighted force scalar times d and the energy kernel.
 template <bool WRAP>
-__device__ __forceinline__ void real_pair(const RealArgs &a, const double4 &me, const double4 &o,
-                                          bool ok, double &fx, double &fy, double &fz,
-                                          double &e) {
+__device__ __forceinline__ void real_pair(const RealArgs &a, const double *tab, const double4 &me,
+                                          const double4 &o, bool ok, double &fx, double &fy,
+                                          double &fz, double &e) {
   double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
   if constexpr (WRAP) {
     dx = min_image(dx, a.b.L[0], a.b.invL[0]);
@@ -87,8 +118,17 @@ __device__ __forceinline__ void real_pair(const RealArgs &a, const double4 &me, 
   const double rr2 = in ? r2 : 1.0;  // keeps padding and far pairs finite
   const double r = __builtin_sqrt(rr2);
   const double ir = recip64(r);
-  const double er = erfc(a.alpha * r) * ir;
-  const double s = (er + a.c2a * exp(-a.a2 * rr2)) * (ir * ir);
+  const double xa = a.alpha * r;
+  int it = (int)(xa * a.inv_dx);
+  it = it < kErfcIntervals - 1 ? it : kErfcIntervals - 1;
+  const double t = xa - (2 * it + 1) * a.half_dx;
+  const double *cf = tab + it * kErfcStride;
+  double p = cf[kErfcDegree];
+#pragma unroll
+  for (int k = kErfcDegree - 1; k >= 0; --k) p = __builtin_fma(p, t, cf[k]);
+  const double ex = exp(-a.a2 * rr2);
+  const double er = ex * p * ir;  // erfc(alpha r) / r
+  const double s = (er + a.c2a * ex) * (ir * ir);
   const double qs = in ? o.w * s : 0.0;
   fx = __builtin_fma(qs, dx, fx);
   fy = __builtin_fma(qs, dy, fy);
@@ -97,9 +137,9 @@ __device__ __forceinline__ void real_pair(const RealArgs &a, const double4 &me, 
 }
 
 template <bool WRAP, bool WIDE>
-__device__ __forceinline__ void real_row(const RealArgs &a, const int32_t *row, int32_t cnt,
-                                         const double4 &me, double &fx, double &fy, double &fz,
-                                         double &e) {
+__device__ __forceinline__ void real_row(const RealArgs &a, const double *tab, const int32_t *row,
+                                         int32_t cnt, const double4 &me, double &fx, double &fy,
+                                         double &fz, double &e) {
   constexpr int U = kEwUnroll;
   constexpr int kStep = kEwTeam * kWave;
   const int32_t whole = cnt - cnt % U;
@@ -112,7 +152,7 @@ __device__ __forceinline__ void real_row(const RealArgs &a, const int32_t *row, 
 #pragma unroll
     for (int u = 0; u < U; ++u) o[u] = *xq_of<WIDE>(a.xq, j[u]);
 #pragma unroll
-    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, me, o[u], true, fx, fy, fz, e);
+    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, tab, me, o[u], true, fx, fy, fz, e);
   }
   if (k < cnt) {
     int32_t j[U];
@@ -129,13 +169,16 @@ __device__ __forceinline__ void real_row(const RealArgs &a, const int32_t *row, 
       if (ok[u]) o[u] = *xq_of<WIDE>(a.xq, j[u]);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, me, o[u], ok[u], fx, fy, fz, e);
+    for (int u = 0; u < U; ++u) real_pair<WRAP>(a, tab, me, o[u], ok[u], fx, fy, fz, e);
   }
 }
 
 template <bool WIDE, bool EV>
 __global__ __launch_bounds__(kEwThreads) void k_ewald_real(RealArgs a) {
   __shared__ double red[kEwThreads / kWave];
+  __shared__ double tab[kErfcTable];
+  for (int k = threadIdx.x; k < kErfcTable; k += kEwThreads) tab[k] = a.erfcx_tab[k];
+  __syncthreads();
   const int t = (int)threadIdx.x % kEwTeam;
   const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kEwAtoms + (int)threadIdx.x / kEwTeam;
   const bool live = i < a.n;
@@ -152,9 +195,9 @@ __global__ __launch_bounds__(kEwThreads) void k_ewald_real(RealArgs a) {
     const int32_t *row =
         a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
     if (interior)
-      real_row<false, WIDE>(a, row, cnt, me, fx, fy, fz, e);
+      real_row<false, WIDE>(a, tab, row, cnt, me, fx, fy, fz, e);
     else
-      real_row<true, WIDE>(a, row, cnt, me, fx, fy, fz, e);
+      real_row<true, WIDE>(a, tab, row, cnt, me, fx, fy, fz, e);
   }
   fx += __shfl_xor(fx, 1, kWave);
   fy += __shfl_xor(fy, 1, kWave);
@@ -505,7 +548,7 @@ void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
 
 size_t ewald_real_workspace(int64_t n) {
   return (size_t)(n > 0 ? n : 0) * sizeof(double4) +
-         (size_t)blocks_of(n, kEwAtoms) * sizeof(double) + 256;
+         (size_t)blocks_of(n, kEwAtoms) * sizeof(double) + kErfcTable * sizeof(double) + 256;
 }
 
 size_t spme_workspace(int64_t n, int64_t npts) {
@@ -532,8 +575,14 @@ int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const d
   a.accumulate = accumulate;
   const unsigned nblk = blocks_of(n, kEwAtoms);
   a.partial = (double *)((char *)ws + (size_t)(n > 0 ? n : 0) * sizeof(double4));
+  double *tab = a.partial + nblk;
+  a.erfcx_tab = tab;
+  const double dx = alpha * rc / kErfcIntervals;
+  a.inv_dx = 1.0 / dx;
+  a.half_dx = 0.5 * dx;
   if (n > 0) {
-    k_pack_xq<<<blocks_of(n, kThreads), kThreads, 0, st>>>((int32_t)n, x, q, (double4 *)ws);
+    k_pack_xq<<<blocks_of(n, kThreads), kThreads, 0, st>>>((int32_t)n, x, q, (double4 *)ws,
+                                                           a.half_dx, tab);
     const bool wide = n > kNarrowAtoms;
     if (e_total) {
       if (wide) k_ewald_real<true, true><<<nblk, kEwThreads, 0, st>>>(a);
