@@ -432,13 +432,19 @@ __global__ __launch_bounds__(kThreads) void k_fft(double2 *g, int axis, int K0, 
   }
 }
 
-// F(Q)(m) *= B(m) C(m); per block 1/2 sum B C |F(Q)|^2 (fixed order)
+// F(Q)(m) *= B(m) C(m); per block 1/2 sum B C |F(Q)|^2 (fixed order).  Each
+// thread takes kInfPerThread points (a block-stride apart), which keeps the
+// number of energy partials, and so the column sum after it, small.
+constexpr int kInfPerThread = 8;
+
 __global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
   __shared__ double red[kThreads / kWave];
   const int64_t npts = (int64_t)a.K[0] * a.K[1] * a.K[2];
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const double V = a.b.L[0] * a.b.L[1] * a.b.L[2];
   double v[1] = {0.0};
-  if (p < npts) {
+  for (int r = 0; r < kInfPerThread; ++r) {
+    const int64_t p = ((int64_t)blockIdx.x * kInfPerThread + r) * blockDim.x + threadIdx.x;
+    if (p >= npts) break;
     const int m0 = (int)(p % a.K[0]);
     const int m1 = (int)((p / a.K[0]) % a.K[1]);
     const int m2 = (int)(p / ((int64_t)a.K[0] * a.K[1]));
@@ -448,12 +454,11 @@ __global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
     const double msq = (f0 * f0 + f1 * f1) + f2 * f2;
     double G = 0.0;
     if (p != 0) {
-      const double V = a.b.L[0] * a.b.L[1] * a.b.L[2];
       const double C = exp(-kPi * kPi * msq / (a.alpha * a.alpha)) / (kPi * V * msq);
       G = C * a.bmod[m0] * a.bmod[kMaxGrid + m1] * a.bmod[2 * kMaxGrid + m2];
     }
     const double2 z = a.grid[p];
-    v[0] = 0.5 * G * (z.x * z.x + z.y * z.y);
+    v[0] += 0.5 * G * (z.x * z.x + z.y * z.y);
     a.grid[p] = make_double2(G * z.x, G * z.y);
   }
   block_sum<kThreads / kWave, 1>(v, red, a.partial + blockIdx.x);
@@ -539,7 +544,7 @@ void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
   k_zero_grid<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a.grid, npts);
   if (a.n > 0) k_spread<N><<<blocks_of(a.n, kWave), kWave, 0, st>>>(a);
   for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, -1.0, st);
-  k_influence<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a);
+  k_influence<<<blocks_of(npts, kThreads * kInfPerThread), kThreads, 0, st>>>(a);
   for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, 1.0, st);
   if (a.n > 0) k_gather<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a, self_partial);
 }
@@ -618,7 +623,7 @@ int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t 
   a.bmod = (double *)p;
   p += 3 * kMaxGrid * sizeof(double);
   a.partial = (double *)p;
-  const unsigned ninf = blocks_of(npts, kThreads);
+  const unsigned ninf = blocks_of(npts, kThreads * kInfPerThread);
   const unsigned ngat = blocks_of(n, kThreads);
   double *self_partial = n > 0 ? a.partial + ninf : nullptr;
   switch (order) {
