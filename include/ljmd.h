@@ -354,7 +354,8 @@ int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double
  *   [8, LJMD_SPME_MAX_GRID]; x [n][3] in [0, L) (any order), q [n].  F receives
  *   the reciprocal-space forces (accumulate as above); e_total (or NULL)
  *   receives E_rec + E_self.  ws >= ljmd_workspace_bytes(LJMD_OP_SPME, n,
- *   K[0]*K[1]*K[2], 0), 32-byte aligned; it holds the complex grid.  The charge
+ *   K[0]*K[1]*K[2], 0), 32-byte aligned; it holds the real charge grid and its
+ *   half-complex transform.  The charge
  *   spreading uses FP64 atomic additions: results agree run to run to rounding,
  *   not bit for bit.
  *   alpha > 0; rc as for the other pair kernels (LJMD_EBOX if too large).

@@ -20,12 +20,16 @@
 // Kernels: the real-space pair loop walks the tiled full list with two lanes
 // per particle over packed (x, y, z, q) records (the SPH and LJ traversal),
 // with erfc taken as e^{-x^2} times a tabulated polynomial for erfcx;
-// charge spreading is one thread per particle with FP64 hardware atomics on
-// the grid; each 3-D transform is three passes of radix-2 FFTs over rows
-// staged in LDS (rows along y and z are loaded with consecutive x across
-// lanes, so every pass reads and writes whole cache lines); the influence
-// function B C is applied in k-space with the energy summed per block in a
-// fixed order; the gather is one thread per particle.
+// charge is spread onto a real grid (LDS-privatised per wavefront, then FP64
+// atomics); the 3-D transform is real-to-complex: the x pass turns each row of
+// K0 reals into K0/2 + 1 coefficients through one complex FFT of length K0/2
+// plus a split step, and the y and z passes run on that half grid, each pass
+// a set of radix-2 FFTs over rows staged in LDS (rows along y and z loaded
+// with consecutive x across lanes, so every pass reads and writes whole cache
+// lines); the influence function B C is applied on the half grid, each
+// coefficient with 0 < m_0 < K0/2 counted twice in the energy (Hermitian
+// symmetry of a real input); the inverse mirrors it and leaves phi real; the
+// gather is one thread per particle.
 #include "common.h"
 
 namespace ljmd {
@@ -33,7 +37,6 @@ namespace ljmd {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kMaxOrder = 8;
 constexpr int kMaxGrid = 256;  // points per edge
 constexpr int kThreads = 256;
 constexpr int kEwAtoms = 256;  // real space: particles per block
@@ -259,7 +262,8 @@ struct RecArgs {
   int32_t n;
   const double *x;
   const double *q;
-  double2 *grid;       // [K2][K1][K0] complex, x fastest
+  double *grid;        // [K2][K1][K0] real: Q, later phi; x fastest
+  double2 *half;       // [K2][K1][K0/2 + 1] complex transform of the grid
   double *bmod;        // |b_a(m)|^2 tables at bmod + a * kMaxGrid
   double *partial;     // influence blocks, then gather blocks
   double *F;
@@ -289,9 +293,9 @@ __global__ __launch_bounds__(kThreads) void k_bmod(RecArgs a) {
   a.bmod[ax * kMaxGrid + m] = 1.0 / (re * re + im * im);
 }
 
-__global__ __launch_bounds__(kThreads) void k_zero_grid(double2 *g, int64_t npts) {
+__global__ __launch_bounds__(kThreads) void k_zero_grid(double *g, int64_t npts) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < npts) g[i] = make_double2(0.0, 0.0);
+  if (i < npts) g[i] = 0.0;
 }
 
 // Charge spreading, one wavefront of 64 consecutive (cell-sorted, hence
@@ -347,10 +351,10 @@ __global__ __launch_bounds__(kWave) void k_spread(RecArgs a) {
       for (int jy = 0; jy < N; ++jy) {
         const int ky = wrapi(b[1] - jy, a.K[1]);
         const double wyz = qi * w[2][jz] * w[1][jy];
-        double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
+        double *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
 #pragma unroll
         for (int jx = 0; jx < N; ++jx)
-          unsafeAtomicAdd(&line[wrapi(b[0] - jx, a.K[0])].x, wyz * w[0][jx]);
+          unsafeAtomicAdd(&line[wrapi(b[0] - jx, a.K[0])], wyz * w[0][jx]);
       }
     }
     return;
@@ -376,48 +380,47 @@ __global__ __launch_bounds__(kWave) void k_spread(RecArgs a) {
     const int k0 = wrapi(lo[0] + l0 - (N - 1) - sh[0], a.K[0]);
     const int k1 = wrapi(lo[1] + l1 - (N - 1) - sh[1], a.K[1]);
     const int k2 = wrapi(lo[2] + l2 - (N - 1) - sh[2], a.K[2]);
-    unsafeAtomicAdd(&a.grid[((int64_t)k2 * a.K[1] + k1) * a.K[0] + k0].x, v);
+    unsafeAtomicAdd(&a.grid[((int64_t)k2 * a.K[1] + k1) * a.K[0] + k0], v);
   }
 }
 
-// Radix-2 transform of rows of length NP along one axis, R rows per block
-// staged in LDS: bit-reversed load, log2(NP) butterfly stages, natural-order
-// store.  sign = -1: sum_k v_k e^{-2 pi i m k / NP}; +1: the unnormalised inverse.
-// rows per block: 1024 points, at most 64 rows (a power of two that divides the
-// row count, which is the product of two edges of at least 8 points each)
+// Radix-2 transforms of rows of length NP, R rows per block staged in LDS:
+// bit-reversed load, log2(NP) butterfly stages, natural-order result.
+// sign = -1: sum_k v_k e^{-2 pi i m k / NP}; +1: the unnormalised inverse.
+// Rows per block: 1024 points, at most 64 rows.
 template <int NP>
 constexpr int fft_rows() {
   return 1024 / NP < 64 ? 1024 / NP : 64;
 }
 
 template <int NP>
-__global__ __launch_bounds__(kThreads) void k_fft(double2 *g, int axis, int K0, int K1,
-                                                  double sign) {
-  constexpr int R = fft_rows<NP>();
-  constexpr int LOG = __builtin_ctz(NP);
-  __shared__ double2 buf[R * NP];
-  const int64_t r0 = (int64_t)blockIdx.x * R;
-  const int64_t plane = (int64_t)K0 * K1;
-  auto addr = [&](int m, int k) -> int64_t {
-    const int64_t r = r0 + m;
-    if (axis == 0) return r * NP + k;
-    if (axis == 1) return (r % K0) + (r / K0) * plane + (int64_t)k * K0;
-    return r + (int64_t)k * plane;
-  };
-  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
-    const int m = axis == 0 ? idx / NP : idx % R;
-    const int k = axis == 0 ? idx % NP : idx / R;
-    const int kr = (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - LOG));
-    buf[m * NP + kr] = g[addr(m, k)];
+__device__ __forceinline__ int bitrev(int k) {
+  return (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - __builtin_ctz(NP)));
+}
+
+// Twiddle table in LDS: tw[j] = e^{sign 2 pi i j / (TS NP)}, j <= TS NP / 2.
+template <int NP, int TS>
+__device__ __forceinline__ void fill_twiddles(double2 *tw, double sign) {
+  for (int j = threadIdx.x; j <= TS * NP / 2; j += kThreads) {
+    double s, c;
+    sincospi(sign * 2.0 * (double)j / (double)(TS * NP), &s, &c);
+    tw[j] = make_double2(c, s);
   }
-  __syncthreads();
+}
+
+// The butterfly stages over R rows of NP points in buf (bit-reversed order in,
+// natural order out); the twiddle of stage h, position pos, e^{sign i pi pos/h},
+// is tw[TS pos NP / (2h)].  Every thread of the block calls it.
+template <int NP, int R, int TS>
+__device__ __forceinline__ void fft_stages(double2 *buf, const double2 *tw) {
   for (int h = 1; h < NP; h <<= 1) {
+    const int step = TS * NP / (2 * h);
     for (int b = threadIdx.x; b < R * NP / 2; b += kThreads) {
       const int m = b / (NP / 2), bb = b % (NP / 2);
       const int pos = bb % h, grp = bb / h;
       const int i0 = m * NP + grp * 2 * h + pos, i1 = i0 + h;
-      double s, c;
-      sincospi(sign * (double)pos / (double)h, &s, &c);
+      const double2 w = tw[pos * step];
+      const double c = w.x, s = w.y;
       const double2 u = buf[i0], v = buf[i1];
       const double tr = c * v.x - s * v.y, ti = c * v.y + s * v.x;
       buf[i0] = make_double2(u.x + tr, u.y + ti);
@@ -425,10 +428,107 @@ __global__ __launch_bounds__(kThreads) void k_fft(double2 *g, int axis, int K0, 
     }
     __syncthreads();
   }
+}
+
+// y (axis 1) or z (axis 2) pass over the half grid of width W = K0/2 + 1:
+// rows r < rows, element k of row r at (r % W) + (r / W) W K1 + k W (axis 1)
+// or r + k W K1 (axis 2); consecutive rows are consecutive x.
+template <int NP>
+__global__ __launch_bounds__(kThreads) void k_fft_yz(double2 *g, int axis, int W, int K1,
+                                                     int64_t rows, double sign) {
+  constexpr int R = fft_rows<NP>();
+  __shared__ double2 buf[R * NP];
+  __shared__ double2 tw[NP / 2 + 1];
+  fill_twiddles<NP, 1>(tw, sign);
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int64_t plane = (int64_t)W * K1;
   for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
-    const int m = axis == 0 ? idx / NP : idx % R;
-    const int k = axis == 0 ? idx % NP : idx / R;
-    g[addr(m, k)] = buf[m * NP + k];
+    const int m = idx % R, k = idx / R;
+    const int64_t r = r0 + m;
+    if (r >= rows) continue;
+    const int64_t at = axis == 1 ? (r % W) + (r / W) * plane + (int64_t)k * W : r + k * plane;
+    buf[m * NP + bitrev<NP>(k)] = g[at];
+  }
+  __syncthreads();
+  fft_stages<NP, R, 1>(buf, tw);
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = idx % R, k = idx / R;
+    const int64_t r = r0 + m;
+    if (r >= rows) continue;
+    const int64_t at = axis == 1 ? (r % W) + (r / W) * plane + (int64_t)k * W : r + k * plane;
+    g[at] = buf[m * NP + k];
+  }
+}
+
+// x pass, real to complex: row r of NP reals -> NP/2 + 1 coefficients X_m =
+// sum_k v_k e^{-2 pi i m k / NP}.  With z_k = v_2k + i v_2k+1 and Z its
+// transform of length NH = NP/2: X_m = E_m + e^{-2 pi i m/NP} O_m, where
+// E_m = (Z_m + conj Z_{NH-m}) / 2 and O_m = (Z_m - conj Z_{NH-m}) / (2i) are the
+// transforms of the even and odd samples (indices of Z mod NH).
+template <int NP>
+__global__ __launch_bounds__(kThreads) void k_fft_x_r2c(const double *rg, double2 *h,
+                                                        int64_t rows) {
+  constexpr int NH = NP / 2;
+  constexpr int R = fft_rows<NH>();
+  __shared__ double2 buf[R * NH];
+  __shared__ double2 tw[NP / 2 + 1];  // e^{-2 pi i j / NP}
+  fill_twiddles<NH, 2>(tw, -1.0);
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  for (int idx = threadIdx.x; idx < R * NH; idx += kThreads) {
+    const int m = idx / NH, k = idx % NH;
+    const int64_t r = r0 + m;
+    if (r >= rows) continue;
+    buf[m * NH + bitrev<NH>(k)] = *(const double2 *)(rg + r * NP + 2 * k);
+  }
+  __syncthreads();
+  fft_stages<NH, R, 2>(buf, tw);
+  for (int idx = threadIdx.x; idx < R * (NH + 1); idx += kThreads) {
+    const int m = idx / (NH + 1), k = idx % (NH + 1);
+    const int64_t r = r0 + m;
+    if (r >= rows) continue;
+    const double2 zm = buf[m * NH + (k % NH)], zc = buf[m * NH + ((NH - k) % NH)];
+    const double er = 0.5 * (zm.x + zc.x), ei = 0.5 * (zm.y - zc.y);
+    const double orr = 0.5 * (zm.y + zc.y), oi = -0.5 * (zm.x - zc.x);
+    const double c = tw[k].x, s = tw[k].y;
+    h[r * (NH + 1) + k] = make_double2(er + (c * orr - s * oi), ei + (c * oi + s * orr));
+  }
+}
+
+// x pass, complex to real: the NP/2 + 1 coefficients X_m of a Hermitian row
+// -> v_k = sum_{m<NP} X_m e^{+2 pi i m k / NP}.  With A_m = X_m + conj X_{NH-m},
+// B_m = (X_m - conj X_{NH-m}) e^{+2 pi i m/NP} for m < NH, the inverse transform
+// of length NH of A + iB is z_k = v_2k + i v_2k+1.
+template <int NP>
+__global__ __launch_bounds__(kThreads) void k_fft_x_c2r(const double2 *h, double *rg,
+                                                        int64_t rows) {
+  constexpr int NH = NP / 2;
+  constexpr int R = fft_rows<NH>();
+  __shared__ double2 xin[R * (NH + 1)];
+  __shared__ double2 buf[R * NH];
+  __shared__ double2 tw[NP / 2 + 1];  // e^{+2 pi i j / NP}
+  fill_twiddles<NH, 2>(tw, 1.0);
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  for (int idx = threadIdx.x; idx < R * (NH + 1); idx += kThreads) {
+    const int m = idx / (NH + 1), k = idx % (NH + 1);
+    const int64_t r = r0 + m;
+    if (r < rows) xin[idx] = h[r * (NH + 1) + k];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < R * NH; idx += kThreads) {
+    const int m = idx / NH, k = idx % NH;
+    const double2 x1 = xin[m * (NH + 1) + k], x2 = xin[m * (NH + 1) + NH - k];
+    const double ar = x1.x + x2.x, ai = x1.y - x2.y;  // X_m + conj X_{NH-m}
+    const double dr = x1.x - x2.x, di = x1.y + x2.y;  // X_m - conj X_{NH-m}
+    const double c = tw[k].x, s = tw[k].y;
+    const double br = c * dr - s * di, bi = c * di + s * dr;
+    buf[m * NH + bitrev<NH>(k)] = make_double2(ar - bi, ai + br);
+  }
+  __syncthreads();
+  fft_stages<NH, R, 2>(buf, tw);
+  for (int idx = threadIdx.x; idx < R * NH; idx += kThreads) {
+    const int m = idx / NH, k = idx % NH;
+    const int64_t r = r0 + m;
+    if (r < rows) *(double2 *)(rg + r * NP + 2 * k) = buf[m * NH + k];
   }
 }
 
@@ -439,16 +539,17 @@ constexpr int kInfPerThread = 8;
 
 __global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
   __shared__ double red[kThreads / kWave];
-  const int64_t npts = (int64_t)a.K[0] * a.K[1] * a.K[2];
+  const int W = a.K[0] / 2 + 1;
+  const int64_t npts = (int64_t)W * a.K[1] * a.K[2];
   const double V = a.b.L[0] * a.b.L[1] * a.b.L[2];
   double v[1] = {0.0};
   for (int r = 0; r < kInfPerThread; ++r) {
     const int64_t p = ((int64_t)blockIdx.x * kInfPerThread + r) * blockDim.x + threadIdx.x;
     if (p >= npts) break;
-    const int m0 = (int)(p % a.K[0]);
-    const int m1 = (int)((p / a.K[0]) % a.K[1]);
-    const int m2 = (int)(p / ((int64_t)a.K[0] * a.K[1]));
-    const double f0 = (m0 <= a.K[0] / 2 ? m0 : m0 - a.K[0]) * a.b.invL[0];
+    const int m0 = (int)(p % W);
+    const int m1 = (int)((p / W) % a.K[1]);
+    const int m2 = (int)(p / ((int64_t)W * a.K[1]));
+    const double f0 = m0 * a.b.invL[0];
     const double f1 = (m1 <= a.K[1] / 2 ? m1 : m1 - a.K[1]) * a.b.invL[1];
     const double f2 = (m2 <= a.K[2] / 2 ? m2 : m2 - a.K[2]) * a.b.invL[2];
     const double msq = (f0 * f0 + f1 * f1) + f2 * f2;
@@ -457,9 +558,11 @@ __global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
       const double C = exp(-kPi * kPi * msq / (a.alpha * a.alpha)) / (kPi * V * msq);
       G = C * a.bmod[m0] * a.bmod[kMaxGrid + m1] * a.bmod[2 * kMaxGrid + m2];
     }
-    const double2 z = a.grid[p];
-    v[0] += 0.5 * G * (z.x * z.x + z.y * z.y);
-    a.grid[p] = make_double2(G * z.x, G * z.y);
+    const double2 z = a.half[p];
+    // 1/2 G |F|^2, doubled for the columns 0 < m0 < K0/2 whose mirror -m0 is not stored
+    const double mult = (m0 == 0 || 2 * m0 == a.K[0]) ? 0.5 : 1.0;
+    v[0] += mult * G * (z.x * z.x + z.y * z.y);
+    a.half[p] = make_double2(G * z.x, G * z.y);
   }
   block_sum<kThreads / kWave, 1>(v, red, a.partial + blockIdx.x);
 }
@@ -485,11 +588,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(RecArgs a, double *self_par
       const int kz = wrapi(base[2] - jz, a.K[2]);
       for (int jy = 0; jy < N; ++jy) {
         const int ky = wrapi(base[1] - jy, a.K[1]);
-        const double2 *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
+        const double *line = a.grid + ((int64_t)kz * a.K[1] + ky) * a.K[0];
         double sx = 0.0, sdx = 0.0;
 #pragma unroll
         for (int jx = 0; jx < N; ++jx) {
-          const double ph = line[wrapi(base[0] - jx, a.K[0])].x;
+          const double ph = line[wrapi(base[0] - jx, a.K[0])];
           sx = __builtin_fma(w[0][jx], ph, sx);
           sdx = __builtin_fma(dw[0][jx], ph, sdx);
         }
@@ -517,24 +620,48 @@ __global__ __launch_bounds__(kThreads) void k_gather(RecArgs a, double *self_par
 }
 
 template <int NP>
-void fft_pass(double2 *g, int axis, const int32_t K[3], double sign, hipStream_t st) {
+void yz_pass(double2 *h, int axis, const int32_t K[3], double sign, hipStream_t st) {
   constexpr int R = fft_rows<NP>();
-  const int64_t rows = (int64_t)K[0] * K[1] * K[2] / NP;
-  k_fft<NP><<<(unsigned)(rows / R), kThreads, 0, st>>>(g, axis, K[0], K[1], sign);
+  const int W = K[0] / 2 + 1;
+  const int64_t rows = (int64_t)W * (axis == 1 ? K[2] : K[1]);
+  k_fft_yz<NP><<<(unsigned)((rows + R - 1) / R), kThreads, 0, st>>>(h, axis, W, K[1], rows, sign);
 }
 
-void fft_axis(double2 *g, int axis, const int32_t K[3], double sign, hipStream_t st) {
+void fft_yz(double2 *h, int axis, const int32_t K[3], double sign, hipStream_t st) {
   switch (K[axis]) {
-    case 8: fft_pass<8>(g, axis, K, sign, st); break;
-    case 16: fft_pass<16>(g, axis, K, sign, st); break;
-    case 32: fft_pass<32>(g, axis, K, sign, st); break;
-    case 64: fft_pass<64>(g, axis, K, sign, st); break;
-    case 128: fft_pass<128>(g, axis, K, sign, st); break;
-    default: fft_pass<256>(g, axis, K, sign, st); break;
+    case 8: yz_pass<8>(h, axis, K, sign, st); break;
+    case 16: yz_pass<16>(h, axis, K, sign, st); break;
+    case 32: yz_pass<32>(h, axis, K, sign, st); break;
+    case 64: yz_pass<64>(h, axis, K, sign, st); break;
+    case 128: yz_pass<128>(h, axis, K, sign, st); break;
+    default: yz_pass<256>(h, axis, K, sign, st); break;
+  }
+}
+
+template <int NP>
+void x_pass(double *g, double2 *h, const int32_t K[3], bool forward, hipStream_t st) {
+  constexpr int R = fft_rows<NP / 2>();
+  const int64_t rows = (int64_t)K[1] * K[2];
+  const unsigned nb = (unsigned)((rows + R - 1) / R);
+  if (forward)
+    k_fft_x_r2c<NP><<<nb, kThreads, 0, st>>>(g, h, rows);
+  else
+    k_fft_x_c2r<NP><<<nb, kThreads, 0, st>>>(h, g, rows);
+}
+
+void fft_x(double *g, double2 *h, const int32_t K[3], bool forward, hipStream_t st) {
+  switch (K[0]) {
+    case 8: x_pass<8>(g, h, K, forward, st); break;
+    case 16: x_pass<16>(g, h, K, forward, st); break;
+    case 32: x_pass<32>(g, h, K, forward, st); break;
+    case 64: x_pass<64>(g, h, K, forward, st); break;
+    case 128: x_pass<128>(g, h, K, forward, st); break;
+    default: x_pass<256>(g, h, K, forward, st); break;
   }
 }
 
 int64_t grid_points(const int32_t K[3]) { return (int64_t)K[0] * K[1] * K[2]; }
+int64_t half_points(const int32_t K[3]) { return (int64_t)(K[0] / 2 + 1) * K[1] * K[2]; }
 unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per > 0 ? (n + per - 1) / per : 1); }
 
 template <int N>
@@ -543,9 +670,13 @@ void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
   k_bmod<N><<<blocks_of(3 * kMaxGrid, kThreads), kThreads, 0, st>>>(a);
   k_zero_grid<<<blocks_of(npts, kThreads), kThreads, 0, st>>>(a.grid, npts);
   if (a.n > 0) k_spread<N><<<blocks_of(a.n, kWave), kWave, 0, st>>>(a);
-  for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, -1.0, st);
-  k_influence<<<blocks_of(npts, kThreads * kInfPerThread), kThreads, 0, st>>>(a);
-  for (int ax = 0; ax < 3; ++ax) fft_axis(a.grid, ax, a.K, 1.0, st);
+  fft_x(a.grid, a.half, a.K, true, st);
+  fft_yz(a.half, 1, a.K, -1.0, st);
+  fft_yz(a.half, 2, a.K, -1.0, st);
+  k_influence<<<blocks_of(half_points(a.K), kThreads * kInfPerThread), kThreads, 0, st>>>(a);
+  fft_yz(a.half, 2, a.K, 1.0, st);
+  fft_yz(a.half, 1, a.K, 1.0, st);
+  fft_x(a.grid, a.half, a.K, false, st);
   if (a.n > 0) k_gather<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a, self_partial);
 }
 
@@ -556,9 +687,13 @@ size_t ewald_real_workspace(int64_t n) {
          (size_t)blocks_of(n, kEwAtoms) * sizeof(double) + kErfcTable * sizeof(double) + 256;
 }
 
+// real grid, half grid (at most npts/2 + npts/8 complex points: K0 >= 8), tables, partials
 size_t spme_workspace(int64_t n, int64_t npts) {
-  return (size_t)npts * sizeof(double2) + 3 * kMaxGrid * sizeof(double) +
-         ((size_t)blocks_of(npts, kThreads) + blocks_of(n, kThreads)) * sizeof(double) + 256;
+  const int64_t half = npts / 2 + npts / 8;
+  return (size_t)npts * sizeof(double) + (size_t)half * sizeof(double2) +
+         3 * kMaxGrid * sizeof(double) +
+         ((size_t)blocks_of(half, kThreads * kInfPerThread) + blocks_of(n, kThreads)) *
+             sizeof(double) + 256;
 }
 
 int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const double *x,
@@ -618,12 +753,14 @@ int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t 
   a.accumulate = accumulate;
   const int64_t npts = grid_points(K);
   char *p = (char *)ws;
-  a.grid = (double2 *)p;
-  p += (size_t)npts * sizeof(double2);
+  a.grid = (double *)p;
+  p += (size_t)npts * sizeof(double);
+  a.half = (double2 *)p;
+  p += (size_t)(npts / 2 + npts / 8) * sizeof(double2);
   a.bmod = (double *)p;
   p += 3 * kMaxGrid * sizeof(double);
   a.partial = (double *)p;
-  const unsigned ninf = blocks_of(npts, kThreads * kInfPerThread);
+  const unsigned ninf = blocks_of(half_points(K), kThreads * kInfPerThread);
   const unsigned ngat = blocks_of(n, kThreads);
   double *self_partial = n > 0 ? a.partial + ninf : nullptr;
   switch (order) {
