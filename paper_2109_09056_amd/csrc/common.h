@@ -110,11 +110,12 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double *red, do
   }
 }
 
-// Column sums over `rows` partial rows of `stride` doubles (stride divides
-// THREADS), one block:  out[q] = scale * sum_r p[r*stride + q] for q < ncols
-// (+= when accumulate).  Thread t reads the flat array at t, t + THREADS, ...
-// (coalesced), so it always sees column t % stride; the THREADS/stride
-// threads of a column are then added in thread order.  Fixed order throughout.
+// Column sums over `rows` partial rows of `stride` doubles (stride a power of
+// two dividing THREADS), one block:  out[q] = scale * sum_r p[r*stride + q] for
+// q < ncols (+= when accumulate).  Thread t reads the flat array at t,
+// t + THREADS, ... (coalesced), so it always sees column t % stride; the
+// THREADS/stride threads of a column are then added by a tree in LDS.  Fixed
+// order throughout.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, int ncols,
                                                    const double *__restrict__ p,
@@ -137,11 +138,11 @@ __global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, in
   }
   part[t] = s;
   __syncthreads();
-  if (t < ncols) {
-    double tot = 0.0;
-    for (int k = t; k < THREADS; k += stride) tot += part[k];
-    out[t] = accumulate ? out[t] + scale * tot : scale * tot;
+  for (int off = THREADS / 2; off >= stride; off >>= 1) {
+    if (t < off) part[t] += part[t + off];
+    __syncthreads();
   }
+  if (t < ncols) out[t] = accumulate ? out[t] + scale * part[t] : scale * part[t];
 }
 
 // Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD b % 8),
