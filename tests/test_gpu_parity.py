@@ -187,6 +187,11 @@ def test_neighbor_capacity_overflow_reported(dev, orc):
     off, nb = orc.neighbor_lists(x, w.box, w.rlist)
     assert int(mc.item()) == int(np.diff(off).max())
     assert int(nnbr.max().item()) == 10
+    # the first 10 entries kept in each cut row are true neighbours
+    got = gpu_pairs_by_id(nbr.cpu().numpy(), nnbr.cpu().numpy(), 10, ids.cpu().numpy())
+    want = oracle_pairs(off, nb)
+    assert got.shape[0] == 10 * x.shape[0]
+    assert np.all(np.isin(got[:, 0] * x.shape[0] + got[:, 1], want[:, 0] * x.shape[0] + want[:, 1]))
     # the driver grows maxn until nothing is cut
     from paper_2109_09056_amd import md
     nl = md.NeighborList(w.box, w.rlist, ops.FULL, maxn=10, device=dev).build(xs, cs)
