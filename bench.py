@@ -346,7 +346,55 @@ def spme_bench(dev, reps=30):
             "value": round(n / (tb * 1e-3), 1), "unit": "atom-evaluations/s",
             "real_GBps": round(br / (tr * 1e-3) / 1e9, 1),
             "recip_GBps": round(bk / (tk * 1e-3) / 1e9, 1),
+            "real_frac": round(br / (tr * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "recip_frac": round(bk / (tk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "energy": [float(v) for v in E.cpu()]}
+
+
+def sph_cpu_oracle(rows=1024):
+    """The SPH oracle (all pairs, FP64, OpenMP) on a sample of the 512,000-particle
+    fluid: density and pressure acceleration of `rows` sampled particles (the
+    acceleration with uniform densities as input: the same pair work)."""
+    import numpy as np
+    import lj_inputs as li
+    import oracle
+    w = li.SPH_WORKLOADS["sph512k"]
+    x = li.sph_positions(w)
+    sel = np.sort(np.random.default_rng(1).choice(w.natoms, rows, replace=False))
+    t0 = time.perf_counter()
+    oracle.sph_density(x, w.box, w.h, w.mass, sel=sel)
+    oracle.sph_accel(x, w.box, w.h, w.mass, w.c0, w.rho0, np.full(w.natoms, w.rho0), sel=sel)
+    dt = time.perf_counter() - t0
+    return {"value": round(rows / dt, 3), "unit": "particle-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"density + acceleration of {rows} sampled particles of "
+                                        f"{w.natoms}, all pairs ({dt:.1f} s)"}
+
+
+def spme_cpu_oracle(rows=256):
+    """The SPME reference steps (NumPy spreading, FFTs, sampled gathers) and the Ewald
+    direct-sum oracle on the same 500,000-charge input: the grid part once, the
+    per-particle parts on `rows` sampled atoms, scaled to one whole evaluation."""
+    import numpy as np
+    import lj_inputs as li
+    import oracle
+    w = li.WORKLOADS["lj500k"]
+    x, q = li.positions(w), li.charges(w)
+    K = li.ewald_grid(w.box)
+    sel = np.sort(np.random.default_rng(2).choice(w.natoms, rows, replace=False))
+    t0 = time.perf_counter()
+    oracle.spme_recip(x, q, w.box, li.EWALD_ALPHA, K, li.EWALD_ORDER, sel=sel[:1])
+    t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.spme_recip(x, q, w.box, li.EWALD_ALPHA, K, li.EWALD_ORDER, sel=sel)
+    t_gather = max(time.perf_counter() - t0 - t_grid, 0.0) / rows
+    t0 = time.perf_counter()
+    oracle.ewald_direct(x, q, w.box, li.EWALD_ALPHA, w.rc, sel=sel)
+    t_direct = (time.perf_counter() - t0) / rows
+    total = t_grid + w.natoms * (t_gather + t_direct)
+    return {"value": round(w.natoms / total, 3), "unit": "atom-evaluations/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"grid part once ({t_grid:.1f} s), gathers and all-pairs direct sums of "
+                      f"{rows} sampled atoms, scaled to {w.natoms} atoms ({total:.0f} s)"}
 
 
 def cpu_baseline(w, s, target_s):
@@ -454,8 +502,12 @@ def main():
         log(f"[bench] 2M atoms: {t2 * 1e3 / w2.steps:.4f} ms/step")
         del sim2, s2
         line["sph_512k"] = sph_bench(dev)
+        if not args.no_cpu_baseline:
+            line["sph_512k"]["cpu_oracle"] = sph_cpu_oracle()
         log(f"[bench] SPH 512k: {line['sph_512k']}")
         line["spme_500k"] = spme_bench(dev)
+        if not args.no_cpu_baseline:
+            line["spme_500k"]["cpu_oracle"] = spme_cpu_oracle()
         log(f"[bench] SPME 500k: {line['spme_500k']}")
         line["shard_share_2x2x2"] = shard_share(dev)
         log(f"[bench] one 2x2x2 shard: {line['shard_share_2x2x2']}")
