@@ -55,6 +55,8 @@ def parse():
                     help="run only the SPH leg (512,000 particles) and print its JSON object")
     ap.add_argument("--spme-only", action="store_true",
                     help="run only the SPME leg (500,000 charges) and print its JSON object")
+    ap.add_argument("--charged-only", action="store_true",
+                    help="run only the charged LJ + SPME MD leg and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (x5), to calibrate HBM "
                          "byte counters")
@@ -351,6 +353,30 @@ def spme_bench(dev, reps=30):
             "energy": [float(v) for v in E.cpu()]}
 
 
+def charged_md_bench(dev, steps=100, warmup=20):
+    """The 500,000-atom LJ liquid with unit charges (half +1, half -1) as CabanaMD
+    composes it: per step LJ forces (mixed) + Ewald real space over the same list +
+    SPME reciprocal part (128^3, order 4), then velocity Verlet; rebuild every 20."""
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import electrostatics as es, ops
+    w = li.WORKLOADS["lj500k"]
+    sim = es.ChargedLJSim(w.box, alpha=li.EWALD_ALPHA, order=li.EWALD_ORDER,
+                          grid=li.ewald_grid(w.box), rc=w.rc, skin=w.skin, precision=ops.MIXED,
+                          dt=w.dt, rebuild_every=w.rebuild_every, device=dev)
+    sim.load(li.positions(w), li.velocities(w), li.charges(w))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    th = sim.thermo()
+    return {"natoms": w.natoms, "steps": steps, "value": round(w.natoms * steps / t, 1),
+            "unit": "atom-steps/s", "ms_per_step": round(t * 1e3 / steps, 5),
+            "grid": list(sim.grid), "order": sim.order, "temp": round(th["temp"], 4)}
+
+
 def sph_cpu_oracle(rows=1024):
     """The SPH oracle (all pairs, FP64, OpenMP) on a sample of the 512,000-particle
     fluid: density and pressure acceleration of `rows` sampled particles (the
@@ -440,6 +466,9 @@ def main():
     if args.spme_only:
         print(json.dumps({"spme_500k": spme_bench(dev)}), flush=True)
         return
+    if args.charged_only:
+        print(json.dumps({"charged_md_500k": charged_md_bench(dev)}), flush=True)
+        return
     w = li.WORKLOADS[args.workload]
     s = li.make_system(w)
     n = w.natoms
@@ -509,6 +538,8 @@ def main():
         if not args.no_cpu_baseline:
             line["spme_500k"]["cpu_oracle"] = spme_cpu_oracle()
         log(f"[bench] SPME 500k: {line['spme_500k']}")
+        line["charged_md_500k"] = charged_md_bench(dev)
+        log(f"[bench] charged LJ + SPME MD 500k: {line['charged_md_500k']}")
         line["shard_share_2x2x2"] = shard_share(dev)
         log(f"[bench] one 2x2x2 shard: {line['shard_share_2x2x2']}")
         log(f"[bench] bwd/fwd: {json.dumps(line['bwd_fwd'])}")

@@ -71,3 +71,11 @@ def max_rel_vec(a, b):
     a = np.asarray(a).reshape(len(a), -1)
     b = np.asarray(b).reshape(len(b), -1)
     return np.linalg.norm(a - b, axis=1).max() / max(np.linalg.norm(b, axis=1).max(), 1e-300)
+
+
+def pairs_within(x, L, rc):
+    """Number of unordered pairs closer than rc (NumPy brute force, small n)."""
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    r2 = (d * d).sum(-1)
+    return int((np.triu(r2 < rc * rc, 1)).sum())

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import lj_inputs as li
-from helpers import gpu_device
+from helpers import gpu_device, pairs_within
 
 pytestmark = pytest.mark.gpu
 
@@ -107,14 +107,6 @@ def test_nve_lj256_matches_oracle_trajectory(dev, orc):
         assert th["pe"] == pytest.approx(pe_o, rel=1e-10)
         assert th["ke"] == pytest.approx(ke_o, rel=1e-10)
     assert th0["temp"] == pytest.approx(1.44, rel=1e-12)
-
-
-def pairs_within(x, L, rc):
-    """Number of unordered pairs closer than rc (NumPy brute force)."""
-    d = x[:, None, :] - x[None, :, :]
-    d -= L * np.round(d / L)
-    r2 = (d * d).sum(-1)
-    return int((np.triu(r2 < rc * rc, 1)).sum())
 
 
 def test_nve_energy_and_momentum_lj256(dev, orc):
