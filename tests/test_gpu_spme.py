@@ -60,7 +60,9 @@ def test_real_space_vs_oracle(dev, orc, name):
 
 
 SPME_CASES = [("lj256", (16, 16, 16), 4), ("gas1000", (16, 32, 8), 6),
-              ("gas1000", (32, 32, 32), 8), ("lj32k", (64, 64, 64), 4)]
+              ("gas1000", (32, 32, 32), 8), ("lj32k", (64, 64, 64), 4),
+              # the smallest and largest x edges (x pass of 4 and 128 complex points)
+              ("lj256", (8, 16, 32), 4), ("gas1000", (256, 8, 16), 6)]
 
 
 @pytest.mark.parametrize("name,K,order", SPME_CASES)
