@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
 # HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
 # gives the two counters); set to None whenever the kernel changes until re-measured.
-FORCE_TRAFFIC = 235.71e6
-FORCE_VALU_BUSY = 0.517
-FORCE_TA_BUSY = 0.732
+FORCE_TRAFFIC = None
+FORCE_VALU_BUSY = None
+FORCE_TA_BUSY = None
 
 
 def log(msg):

@@ -22,7 +22,7 @@ namespace ljmd {
 
 namespace {
 
-constexpr int kThreads = 256;  // atoms per block
+constexpr int kThreads = 128;  // atoms per block
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTeam = 2;       // lanes per atom for one or two types
 

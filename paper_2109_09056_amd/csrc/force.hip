@@ -28,7 +28,7 @@
 
 namespace ljmd {
 
-constexpr int kForceThreads = 256;
+constexpr int kForceThreads = 128;
 constexpr int kForceWaves = kForceThreads / kWave;
 constexpr int kEvStride = 8;  // partial row: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, pad
 
@@ -565,8 +565,9 @@ __global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
 // Loop shapes, measured on MI355X.  One lane per atom (the CSR kernel with
 // team 1): 8 slots per group, against 1, 2 and 4.  Tiled full list: two lanes
 // per atom with 6 slots per group each, against one lane with 8 slots and
-// teams of 4 (fewer cache lines per gather instruction, with the
-// energy/virial partials still summed over 256 atoms per block).
+// teams of 4 (fewer cache lines per gather instruction); 128 atoms (256
+// threads) per block, against 64 and 256 atoms (more resident blocks per CU
+// hide more gather latency; 64 pays for its extra energy/virial partial rows).
 constexpr int kUnroll = 8;
 constexpr int kTeam = 2;
 constexpr int kTeamUnroll = 6;

@@ -14,7 +14,7 @@
 //
 // Traversal as in the LJ force kernel: two lanes per particle over its row of
 // the 64-particle tile (entries t, t + 2, ...), six gathers in flight per
-// lane, a butterfly to combine the team, 256 particles per block, blocks
+// lane, a butterfly to combine the team, 128 particles per block, blocks
 // renumbered per XCD; no atomics, so results are bitwise reproducible.  The
 // acceleration pass first packs (x, y, z, P) per particle into 32-byte
 // records in the workspace: a neighbour then costs two 16-byte gathers
@@ -25,7 +25,7 @@ namespace ljmd {
 
 namespace {
 
-constexpr int kSphAtoms = 256;  // particles per block
+constexpr int kSphAtoms = 128;  // particles per block
 constexpr int kSphTeam = 2;     // lanes per particle
 constexpr int kSphThreads = kSphAtoms * kSphTeam;
 constexpr int kSphWaves = kSphThreads / kWave;

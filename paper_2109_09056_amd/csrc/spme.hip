@@ -39,7 +39,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxGrid = 256;  // points per edge
 constexpr int kThreads = 256;
-constexpr int kEwAtoms = 256;  // real space: particles per block
+constexpr int kEwAtoms = 128;  // real space: particles per block
 constexpr int kEwTeam = 2;
 constexpr int kEwThreads = kEwAtoms * kEwTeam;
 constexpr int kEwUnroll = 6;
