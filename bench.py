@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
 # HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
 # gives the two counters); set to None whenever the kernel changes until re-measured.
-FORCE_TRAFFIC = None
-FORCE_VALU_BUSY = None
-FORCE_TA_BUSY = None
+FORCE_TRAFFIC = 232.55e6
+FORCE_VALU_BUSY = 0.546
+FORCE_TA_BUSY = 0.766
 
 
 def log(msg):
@@ -377,7 +377,7 @@ def charged_md_bench(dev, steps=100, warmup=20):
             "grid": list(sim.grid), "order": sim.order, "temp": round(th["temp"], 4)}
 
 
-def sph_cpu_oracle(rows=1024):
+def sph_cpu_oracle(rows=4096):
     """The SPH oracle (all pairs, FP64, OpenMP) on a sample of the 512,000-particle
     fluid: density and pressure acceleration of `rows` sampled particles (the
     acceleration with uniform densities as input: the same pair work)."""

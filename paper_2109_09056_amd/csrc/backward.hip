@@ -375,7 +375,7 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
     if (mixed) LJMD_VJP(true, 0, 1); else LJMD_VJP(false, 0, 1);
   }
 #undef LJMD_VJP
-  k_colsum<256><<<1, 256, 0, st>>>(nblk, stride, cols, a.partial, colsums, 1.0, 0);
+  k_colsum<1024><<<1, 1024, 0, st>>>(nblk, stride, cols, a.partial, colsums, 1.0, 0);
   k_param_finalize<<<1, 128, 0, st>>>(ntypes, colsums, geps, gsig, accumulate);
   return check_launch("ljmd_force_backward");
 }

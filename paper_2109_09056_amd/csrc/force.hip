@@ -28,8 +28,10 @@
 
 namespace ljmd {
 
-constexpr int kForceThreads = 128;
+constexpr int kForceThreads = 128;  // atoms per block of the tiled kernels
 constexpr int kForceWaves = kForceThreads / kWave;
+constexpr int kCsrThreads = 256;    // threads per block of the CSR kernel (256 / team atoms)
+constexpr int kCsrWaves = kCsrThreads / kWave;
 constexpr int kEvStride = 8;  // partial row: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, pad
 
 struct ForceArgs {
@@ -447,18 +449,18 @@ __global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
 // same team size the two kernels give bitwise the same forces and per-atom
 // energies.
 template <bool MIXED, bool T1, bool EV, int TEAM, int U, bool WIDE>
-__global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
+__global__ __launch_bounds__(kCsrThreads) void k_force_csr(ForceArgs a,
                                                             const int64_t *__restrict__ off,
                                                             const int32_t *__restrict__ csr) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
-  __shared__ double red[kForceWaves * 8];
+  __shared__ double red[kCsrWaves * 8];
   Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
   } else {
     load_table(a, tab);
   }
-  constexpr int kAtoms = kForceThreads / TEAM;  // atoms per block
+  constexpr int kAtoms = kCsrThreads / TEAM;  // atoms per block
   const int t = threadIdx.x % TEAM;
   const int64_t i64 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAtoms + threadIdx.x / TEAM;
   const bool live = i64 < a.n;
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(kForceThreads) void k_force_csr(ForceArgs a,
     const double v[7] = {lead ? 0.5 * s.e : z,   lead ? 0.5 * s.wxx : z, lead ? 0.5 * s.wyy : z,
                          lead ? 0.5 * s.wzz : z, lead ? 0.5 * s.wxy : z, lead ? 0.5 * s.wxz : z,
                          lead ? 0.5 * s.wyz : z};
-    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+    block_sum<kCsrWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
   }
 }
 
@@ -636,13 +638,14 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   } else if (ev) {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
   }
-  if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
+  if (ev)
+    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces");
 }
 
-// CSR forces: blocks of kForceThreads / team atoms.
+// CSR forces: blocks of kCsrThreads / team atoms.
 unsigned csr_force_blocks(int64_t n, int team) {
-  const int64_t apb = kForceThreads / team;
+  const int64_t apb = kCsrThreads / team;
   const int64_t b = (n + apb - 1) / apb;
   return (unsigned)(b > 0 ? b : 1);
 }
@@ -657,9 +660,9 @@ void launch_csr_team(const ForceArgs &a, const int64_t *off, const int32_t *csr,
   constexpr int U = TEAM == 1 ? kUnroll : 4;
   const unsigned nblk = csr_force_blocks(a.n, TEAM);
   if (a.n <= kNarrowAtoms)
-    k_force_csr<MIXED, T1, EV, TEAM, U, false><<<nblk, kForceThreads, 0, st>>>(a, off, csr);
+    k_force_csr<MIXED, T1, EV, TEAM, U, false><<<nblk, kCsrThreads, 0, st>>>(a, off, csr);
   else
-    k_force_csr<MIXED, T1, EV, TEAM, U, true><<<nblk, kForceThreads, 0, st>>>(a, off, csr);
+    k_force_csr<MIXED, T1, EV, TEAM, U, true><<<nblk, kCsrThreads, 0, st>>>(a, off, csr);
 }
 
 template <bool MIXED, bool T1, bool EV>
@@ -712,7 +715,8 @@ int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, c
   } else if (ev) {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
   }
-  if (ev) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
+  if (ev)
+    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces_csr");
 }
 
@@ -766,7 +770,7 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
   }
 #undef LJMD_STEP
-  k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 8, a.partial, ev, 1.0, 0);
+  k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 8, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_md_step");
 }
 

@@ -185,7 +185,7 @@ int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n
     else if (n > 0)
       k_kick<false><<<nb, kThreads, 0, st>>>(m3, hdt, mass, unit, v, F, partial);
   }
-  if (ke) k_colsum<kThreads><<<1, kThreads, 0, st>>>(nb, 1, 1, partial, ke, 0.5 * mass, 0);
+  if (ke) k_colsum<1024><<<1, 1024, 0, st>>>(nb, 1, 1, partial, ke, 0.5 * mass, 0);
   return check_launch("ljmd_integrate");
 }
 
@@ -201,7 +201,7 @@ int launch_loss(const BoxK &b, int64_t n, const double *x, const double *xref, d
   const unsigned nb = nblocks(3 * n);
   double *partial = (double *)ws;
   k_loss<<<nb, kThreads, 0, st>>>(3 * n, b, x, xref, xbar, partial);
-  k_colsum<kThreads><<<1, kThreads, 0, st>>>(nb, 1, 1, partial, loss, 0.5, 0);
+  k_colsum<1024><<<1, 1024, 0, st>>>(nb, 1, 1, partial, loss, 0.5, 0);
   return check_launch("ljmd_traj_loss");
 }
 

@@ -346,7 +346,8 @@ int launch_sph_density(const BoxK &b, double h, double mass, double c0, double r
       else k_sph_density<false, false><<<nblk, kSphThreads, 0, st>>>(a);
     }
   }
-  if (u_total) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 0, 1, 1, a.partial, u_total, 1.0, 0);
+  if (u_total)
+    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 0, 1, 1, a.partial, u_total, 1.0, 0);
   return check_launch("ljmd_sph_density");
 }
 

@@ -732,7 +732,8 @@ int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const d
       else k_ewald_real<false, false><<<nblk, kEwThreads, 0, st>>>(a);
     }
   }
-  if (e_total) k_colsum<256><<<1, 256, 0, st>>>(n > 0 ? nblk : 0, 1, 1, a.partial, e_total, 1.0, 0);
+  if (e_total)
+    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 0, 1, 1, a.partial, e_total, 1.0, 0);
   return check_launch("ljmd_ewald_real");
 }
 
@@ -769,7 +770,7 @@ int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t 
     default: launch_rec_order<8>(a, self_partial, st); break;
   }
   if (e_total)
-    k_colsum<256><<<1, 256, 0, st>>>((int64_t)ninf + (n > 0 ? ngat : 0), 1, 1, a.partial, e_total,
+    k_colsum<1024><<<1, 1024, 0, st>>>((int64_t)ninf + (n > 0 ? ngat : 0), 1, 1, a.partial, e_total,
                                      1.0, 0);
   return check_launch("ljmd_spme_recip");
 }
