@@ -16,6 +16,9 @@
  *   ljmd_compute_forces   12-6 LJ forces, per-atom energy, energy + virial
  *   ljmd_integrate        velocity-Verlet half kick + drift + wrap / half kick
  *   ljmd_md_step          forces and both half kicks + drift of one step, fused
+ *   ljmd_md_step_chained, ljmd_md_step_sums
+ *                         the same step with its energy sums formed during the
+ *                         next step's launch (one launch per step)
  *   ljmd_list_to_csr, ljmd_compute_forces_csr
  *                         compressed list form and team-per-atom traversal
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
@@ -89,6 +92,7 @@ extern "C" {
 #define LJMD_OP_SPH 7        /* ljmd_sph_density (with u_total), ljmd_sph_accel */
 #define LJMD_OP_EWALD_REAL 8 /* ljmd_ewald_real */
 #define LJMD_OP_SPME 9       /* ljmd_spme_recip; ncells = K[0]*K[1]*K[2] grid points */
+#define LJMD_OP_MD_CHAIN 10  /* ljmd_md_step_chained, ljmd_md_step_sums (two halves) */
 #define LJMD_SPME_MAX_GRID 256 /* largest grid edge of ljmd_spme_recip */
 
 #define LJMD_MAX_TYPES 8
@@ -260,6 +264,40 @@ int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
                  const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
                  int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
                  double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_md_step_chained -- ljmd_md_step without its own column-sum launch: the
+ * step's energy/virial/kinetic partial rows (one per block) stay in half `half`
+ * of ws, and the launch's first workgroup also sums the rows the previous
+ * chained call left in the other half into ev_prev.  A run of steps alternates
+ * half = 0, 1, 0, ... and so costs one launch per step; the sums of the last
+ * step come from ljmd_md_step_sums.  Positions, velocities, forces and per-atom
+ * energies are bitwise those of ljmd_md_step, and so are the sums from
+ * ljmd_md_step_sums; ev_prev holds the same totals added in another order
+ * (equal to rounding).  Same paper passage as ljmd_md_step.
+ *   half     0 or 1: the half of ws that receives this step's partial rows
+ *   ev_prev  [8] output: E, W (6), kinetic energy of the previous step, summed
+ *            from the other half, or NULL when there is no previous step (the
+ *            other half is then not read).  The previous call must have had the
+ *            same n and the other half, and must precede this one on the stream.
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_MD_CHAIN, n, 0, ntypes), kept
+ *            between the calls of a run
+ * Other arguments as in ljmd_md_step.
+ */
+int ljmd_md_step_chained(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                         const double *eps_packed, const double *sigma_packed, int64_t n,
+                         const double *x, const int32_t *type, const int32_t *nbr,
+                         const int32_t *nnbr, int32_t maxn, double dt, double mass, double *v,
+                         double *x_next, int open_next, double *F, double *e_atom, int half,
+                         double *ev_prev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_md_step_sums -- ev [8] (E, W (6), kinetic energy) of the ljmd_md_step_chained
+ * call that wrote half `half` of ws, with n atoms; bitwise the ev of ljmd_md_step
+ * on the same step.  ws as in that call.
+ */
+int ljmd_md_step_sums(int64_t n, int half, const void *ws, size_t ws_bytes, double *ev,
+                      void *stream);
 
 /*
  * ljmd_list_to_csr -- compressed (CSR) copy of a tiled neighbor list (paper:

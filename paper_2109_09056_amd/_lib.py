@@ -18,7 +18,7 @@ FP64, MIXED = 0, 1
 FULL, HALF = 0, 1
 KICK_DRIFT, KICK, KINETIC, KICK_KICK_DRIFT = 0, 1, 2, 3
 (OP_BIN, OP_FORCES, OP_BACKWARD, OP_INTEGRATE, OP_LOSS, OP_CSR, OP_FORCES_CSR, OP_SPH,
- OP_EWALD_REAL, OP_SPME) = range(10)
+ OP_EWALD_REAL, OP_SPME, OP_MD_CHAIN) = range(11)
 SPME_MAX_GRID = 256
 MAX_TYPES = 8
 TILE = 64
@@ -52,6 +52,9 @@ SIGNATURES = {
                                    _p, _p, _p, _p, _int, _p, _sz, _p]),
     "ljmd_md_step": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32, _dbl,
                             _dbl, _p, _p, _int, _p, _p, _p, _p, _sz, _p]),
+    "ljmd_md_step_chained": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32,
+                                    _dbl, _dbl, _p, _p, _int, _p, _p, _int, _p, _p, _sz, _p]),
+    "ljmd_md_step_sums": (_int, [_i64, _int, _p, _sz, _p, _p]),
     "ljmd_list_to_csr": (_int, [_i64, _p, _p, _i32, _p, _p, _i64, _p, _sz, _p]),
     "ljmd_compute_forces_csr": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p,
                                        _i32, _p, _p, _p, _p, _sz, _p]),

@@ -25,7 +25,8 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
                    const double *sig, int64_t n, const double *x, const int32_t *type,
                    const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double dt, double mass,
                    double *v, double *x_next, int open_next, double *F, double *e_atom, double *ev,
-                   void *ws, hipStream_t st);
+                   double *partial, const double *prev_partial, double *prev_ev, hipStream_t st);
+int launch_md_step_sums(int64_t n, const double *partial, double *ev, hipStream_t st);
 size_t bwd_workspace(int64_t n, int32_t ntypes);
 int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
                     const double *sig, int64_t n, const double *x, const int32_t *type,
@@ -159,6 +160,30 @@ using namespace ljmd;
     if (rc_ != LJMD_OK) return rc_; \
   } while (0)
 
+// Arguments common to ljmd_md_step and ljmd_md_step_chained.
+static int check_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                         const double *eps_packed, const double *sigma_packed, int64_t n,
+                         const double *x, const int32_t *type, const int32_t *nbr,
+                         const int32_t *nnbr, int32_t maxn, double dt, double mass,
+                         const double *v, const double *x_next, int open_next) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (!isfinite(dt) || dt == 0.0) return set_error(LJMD_EINVAL, "dt = %g", dt);
+  if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g", mass);
+  if (open_next != 0 && open_next != 1)
+    return set_error(LJMD_EINVAL, "open_next = %d must be 0 or 1", open_next);
+  if (n > 0 && (!x || !nbr || !nnbr || !v || (open_next && !x_next)))
+    return set_error(LJMD_EINVAL, "x/nbr/nnbr/v/x_next is NULL");
+  if (n > 0 && open_next && x_next == x)
+    return set_error(LJMD_EINVAL, "x_next must not alias x");
+  return LJMD_OK;
+}
+
 extern "C" {
 
 const char *ljmd_error_string(int code) {
@@ -189,6 +214,7 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
   switch (op) {
     case LJMD_OP_BIN: return bin_workspace(n, ncells > 0 ? ncells : 1);
     case LJMD_OP_FORCES: return force_workspace(n);
+    case LJMD_OP_MD_CHAIN: return 2 * force_workspace(n);
     case LJMD_OP_BACKWARD:
       return bwd_workspace(n, ntypes < 1 ? 1 : (ntypes > LJMD_MAX_TYPES ? LJMD_MAX_TYPES : ntypes));
     case LJMD_OP_INTEGRATE:
@@ -403,26 +429,40 @@ int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
                  const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
                  int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
                  double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream) {
-  LJMD_TRY(check_box(box));
-  LJMD_TRY(check_cutoff(box, rc, "rc"));
-  LJMD_TRY(check_n(n));
-  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
-    return set_error(LJMD_EINVAL, "bad precision %d", precision);
-  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
-  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
-  if (!isfinite(dt) || dt == 0.0) return set_error(LJMD_EINVAL, "dt = %g", dt);
-  if (!(mass > 0.0) || !isfinite(mass)) return set_error(LJMD_EINVAL, "mass = %g", mass);
-  if (open_next != 0 && open_next != 1)
-    return set_error(LJMD_EINVAL, "open_next = %d must be 0 or 1", open_next);
+  LJMD_TRY(check_md_step(box, precision, rc, ntypes, eps_packed, sigma_packed, n, x, type, nbr,
+                         nnbr, maxn, dt, mass, v, x_next, open_next));
   if (!ev) return set_error(LJMD_EINVAL, "ev is NULL");
-  if (n > 0 && (!x || !nbr || !nnbr || !v || (open_next && !x_next)))
-    return set_error(LJMD_EINVAL, "x/nbr/nnbr/v/x_next is NULL");
-  if (n > 0 && open_next && x_next == x)
-    return set_error(LJMD_EINVAL, "x_next must not alias x");
   LJMD_TRY(check_ws(ws, ws_bytes, force_workspace(n)));
   return launch_md_step(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x, type,
-                        nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, ev, ws,
-                        (hipStream_t)stream);
+                        nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, ev,
+                        (double *)ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int ljmd_md_step_chained(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                         const double *eps_packed, const double *sigma_packed, int64_t n,
+                         const double *x, const int32_t *type, const int32_t *nbr,
+                         const int32_t *nnbr, int32_t maxn, double dt, double mass, double *v,
+                         double *x_next, int open_next, double *F, double *e_atom, int half,
+                         double *ev_prev, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_md_step(box, precision, rc, ntypes, eps_packed, sigma_packed, n, x, type, nbr,
+                         nnbr, maxn, dt, mass, v, x_next, open_next));
+  if (half != 0 && half != 1) return set_error(LJMD_EINVAL, "half = %d must be 0 or 1", half);
+  LJMD_TRY(check_ws(ws, ws_bytes, 2 * force_workspace(n)));
+  double *rows = (double *)ws;
+  const size_t h = force_workspace(n) / sizeof(double);
+  return launch_md_step(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x, type,
+                        nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, nullptr,
+                        rows + half * h, rows + (1 - half) * h, ev_prev, (hipStream_t)stream);
+}
+
+int ljmd_md_step_sums(int64_t n, int half, const void *ws, size_t ws_bytes, double *ev,
+                      void *stream) {
+  LJMD_TRY(check_n(n));
+  if (half != 0 && half != 1) return set_error(LJMD_EINVAL, "half = %d must be 0 or 1", half);
+  if (!ev) return set_error(LJMD_EINVAL, "ev is NULL");
+  LJMD_TRY(check_ws(const_cast<void *>(ws), ws_bytes, 2 * force_workspace(n)));
+  const size_t h = force_workspace(n) / sizeof(double);
+  return launch_md_step_sums(n, (const double *)ws + half * h, ev, (hipStream_t)stream);
 }
 
 int ljmd_force_backward(const ljmd_box *box, int precision, double rc, int32_t ntypes,

@@ -55,6 +55,10 @@ struct ForceArgs {
   double *x_next;
   double dt, hdt, mass;
   int unit_mass, open_next;
+  // chained steps: block 0 also sums the previous step's partial rows into prev_ev
+  const double *prev_partial;
+  double *prev_ev;
+  int64_t prev_rows;
 };
 
 namespace {
@@ -273,10 +277,54 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
 // operations of ljmd_integrate, so the trajectory is bitwise the same as the
 // unfused calls; lane t handles components t, t + TEAM, ...  Partial rows
 // then carry the kinetic energy in column 7.
+// Column sums of `rows` partial rows of kEvStride doubles by the THREADS threads
+// of one block, out[q] = sum_r p[r*kEvStride + q] for q < kEvStride: thread t
+// reads the flat array at t, t + THREADS, ... (column t % kEvStride), the lanes
+// of one column meet by shuffles, the waves in LDS (`lds`: THREADS/64*kEvStride
+// doubles).  Fixed order; every thread of the block calls it.
+template <int THREADS>
+__device__ void block_colsum(const double *__restrict__ p, int64_t rows, double *__restrict__ out,
+                             double *lds) {
+  static_assert(THREADS % kWave == 0 && kWave % kEvStride == 0, "column per lane");
+  const int t = threadIdx.x;
+  const int64_t total = rows * kEvStride;
+  double s = 0.0;
+  constexpr int B = 8;  // loads in flight per thread
+  for (int64_t f0 = t; f0 < total; f0 += (int64_t)B * THREADS) {
+    double v[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int64_t f = f0 + (int64_t)k * THREADS;
+      v[k] = f < total ? p[f] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) s += v[k];
+  }
+#pragma unroll
+  for (int mask = kWave / 2; mask >= kEvStride; mask >>= 1) s += __shfl_xor(s, mask, kWave);
+  const int w = t / kWave, l = t % kWave;
+  if (l < kEvStride) lds[w * kEvStride + l] = s;
+  __syncthreads();
+  if (t < kEvStride) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < THREADS / kWave; ++q) r += lds[q * kEvStride + t];
+    out[t] = r;
+  }
+}
+
 template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE, int TEAM>
 __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a) {
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
   __shared__ double red[kForceWaves * TEAM * 8];
+  if constexpr (STEP) {
+    // chained steps: the previous launch's partial rows are complete (stream
+    // order); block 0 is dispatched first, so its extra pass is off the tail
+    if (a.prev_ev && blockIdx.x == 0) {  // block-uniform
+      block_colsum<kForceThreads * TEAM>(a.prev_partial, a.prev_rows, a.prev_ev, red);
+      __syncthreads();  // `red` is read above and written again by block_sum
+    }
+  }
   Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
@@ -720,11 +768,14 @@ int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, c
   return check_launch("ljmd_compute_forces_csr");
 }
 
+// partial: this step's partial rows; ev: their sums, or NULL to leave them in
+// `partial`; prev_partial/prev_ev: the rows a previous step left and the output of
+// their sums (NULL: none).
 int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
                    const double *sig, int64_t n, const double *x, const int32_t *type,
                    const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double dt, double mass,
                    double *v, double *x_next, int open_next, double *F, double *e_atom, double *ev,
-                   void *ws, hipStream_t st) {
+                   double *partial, const double *prev_partial, double *prev_ev, hipStream_t st) {
   ForceArgs a{};
   a.b = b;
   a.rc = rc;
@@ -740,7 +791,7 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
   a.maxn = maxn;
   a.F = F;
   a.e_atom = e_atom;
-  a.partial = (double *)ws;
+  a.partial = partial;
   a.v = v;
   a.x_next = x_next;
   a.dt = dt;
@@ -749,6 +800,9 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
   a.unit_mass = mass == 1.0;
   a.open_next = open_next;
   const unsigned nblk = force_blocks(n);
+  a.prev_partial = prev_partial;
+  a.prev_ev = prev_ev;
+  a.prev_rows = nblk;
   const bool mixed = precision == LJMD_MIXED;
   const bool t1 = ntypes == 1;
 #define LJMD_STEP(M, T)                                                                    \
@@ -768,10 +822,17 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
     }
   } else {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
+    if (prev_ev) k_colsum<1024><<<1, 1024, 0, st>>>(1, kEvStride, 8, prev_partial, prev_ev, 1.0, 0);
   }
 #undef LJMD_STEP
-  k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 8, a.partial, ev, 1.0, 0);
+  if (ev) k_colsum<1024><<<1, 1024, 0, st>>>(nblk, kEvStride, 8, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_md_step");
+}
+
+// The sums of the partial rows one md_step launch left (same form as its own).
+int launch_md_step_sums(int64_t n, const double *partial, double *ev, hipStream_t st) {
+  k_colsum<1024><<<1, 1024, 0, st>>>(force_blocks(n), kEvStride, 8, partial, ev, 1.0, 0);
+  return check_launch("ljmd_md_step_sums");
 }
 
 }  // namespace ljmd

@@ -134,7 +134,7 @@ class LJSim:
         self._fargs = {}
         self._graphs = {}
         self.cell_start = None
-        for op in (ops.OP_FORCES, ops.OP_INTEGRATE):
+        for op in (ops.OP_FORCES, ops.OP_INTEGRATE, ops.OP_MD_CHAIN):
             self._ws[op] = torch.empty(max(ops.workspace_bytes(op, n), 8), dtype=torch.uint8,
                                        device=dev)
         self.rebuild()
@@ -196,6 +196,23 @@ class LJSim:
             self._fargs[key] = (head + (1,) + tail, head + (0,) + tail)
         return self._fargs[key]
 
+    def _chained_args(self, energy, half, first):
+        """ljmd_md_step_chained argument tuples (opening the next step, closing the call)
+        writing partial rows to `half`; unless `first`, the launch also sums the
+        other half into ev.  Cached per buffer until the next rebuild."""
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        key = ("chain", self.x.data_ptr(), energy, stream, half, first)
+        if key not in self._fargs:
+            p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+            ws = self._ws[ops.OP_MD_CHAIN]
+            head = (ctypes.byref(self._box), self.precision, self.rc, self.ntypes, p(self.eps),
+                    p(self.sigma), self.n, p(self.x), p(self.types), p(self.nl.nbr),
+                    p(self.nl.nnbr), self.nl.maxn, self.dt, self.mass, p(self.v), p(self.xn))
+            tail = (p(self.F), p(self.e_atom) if energy else None, half,
+                    None if first else p(self.ev), p(ws), ws.numel(), ctypes.c_void_p(stream))
+            self._fargs[key] = (head + (1,) + tail, head + (0,) + tail)
+        return self._fargs[key]
+
     def _window_graph(self, m, energy):
         """HIP graph of m fused steps that each open the next one, from the current
         buffers; captured once per buffer arrangement and replayed afterwards."""
@@ -215,7 +232,8 @@ class LJSim:
             self._graphs[key] = g
         return g
 
-    def step(self, nsteps=1, energy=True, force_events=None, graphs=False, on_positions=None):
+    def step(self, nsteps=1, energy=True, force_events=None, graphs=False, on_positions=None,
+             chain=True):
         """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
         (the per-atom energy only when energy is true).
 
@@ -227,6 +245,10 @@ class LJSim:
         trajectory as launching them one by one).  on_positions: optional callable
         given, for every step in order, the positions tensor the force call of that
         step reads (valid until the next launch on the stream; clone to keep it).
+        chain: launched steps run as ljmd_md_step_chained, each summing the previous
+        step's energy/virial/KE rows in its own launch (one launch per step); the last
+        step's sums come from ljmd_md_step_sums, so E, W and KE are bitwise those of
+        ljmd_md_step.
         """
         if nsteps <= 0:
             return self
@@ -235,6 +257,11 @@ class LJSim:
             return self._step_unfused(nsteps, energy, force_events, on_positions)
         integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
         use_graphs = graphs and force_events is None and on_positions is None
+        if chain and not use_graphs:
+            mdstep = lib.ljmd_md_step_chained
+        else:
+            chain = False
+        half = None  # half of the chained workspace the previous launch wrote
         kd = self._step_args(energy)[0]
         _lib.check(integrate(*kd), "ljmd_integrate")
         s = 0
@@ -253,7 +280,12 @@ class LJSim:
                 s += m
                 continue
             last = s == nsteps - 1
-            args = self._fused_args(energy)[1 if last else 0]
+            if chain:
+                first = half is None
+                half = 0 if first else 1 - half
+                args = self._chained_args(energy, half, first)[1 if last else 0]
+            else:
+                args = self._fused_args(energy)[1 if last else 0]
             ab = next(force_events) if force_events is not None else None
             if ab is not None:
                 ab[0].record()
@@ -261,6 +293,8 @@ class LJSim:
                 ab[1].record()
             else:
                 _lib.check(mdstep(*args), "ljmd_md_step")
+            if chain and last:
+                ops.md_step_sums(self.n, half, self._ws[ops.OP_MD_CHAIN], ev=self.ev)
             if on_positions is not None:
                 on_positions(self.x)
             if not last:

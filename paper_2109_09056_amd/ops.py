@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
                    MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
-                   OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_SPH, OP_SPME,
+                   OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_MD_CHAIN, OP_SPH, OP_SPME,
                    SPME_MAX_GRID, TILE, LjmdError, make_box)
 
 
@@ -239,6 +239,63 @@ def md_step(L, precision, rc, eps, sigma, x, types, nbr, nnbr, maxn, dt, mass, v
         _ptr(x_next), 1 if open_next else 0, _ptr(F), _ptr(e_atom), _ptr(ev), _ptr(ws), need,
         _stream(dev)), "ljmd_md_step")
     return x_next, F, ev
+
+
+def _chain_ws(n, ws, dev):
+    """Byte size of the OP_MD_CHAIN workspace, checked against ws: the rows of a run
+    live there between calls, so a fresh one cannot be substituted."""
+    need = int(_lib.load().ljmd_workspace_bytes(OP_MD_CHAIN, n, 0, 1))
+    if ws is None:
+        raise ValueError("the chained steps need the workspace kept between the steps of a run")
+    _need(ws, "ws", torch.uint8, None, dev)
+    if ws.numel() < need:
+        raise ValueError(f"ws holds {ws.numel()} bytes, {need} needed")
+    return need
+
+
+def md_step_chained(L, precision, rc, eps, sigma, x, types, nbr, nnbr, maxn, dt, mass, v, half,
+                    ws, x_next=None, open_next=True, F=None, e_atom=None, ev_prev=None):
+    """md_step whose energy/virial/KE partial rows stay in half `half` of ws (an
+    OP_MD_CHAIN workspace); its first workgroup sums the other half, left by the
+    previous chained step, into ev_prev when given.  Returns x_next."""
+    n = x.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (n, 3))
+    _need(v, "v", torch.float64, (n, 3), dev)
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if open_next and x_next is None:
+        x_next = torch.empty_like(x)
+    _need(x_next, "x_next", torch.float64, (n, 3), dev)
+    _need(F, "F", torch.float64, (n, 3), dev)
+    _need(e_atom, "e_atom", torch.float64, (n,), dev)
+    _need(ev_prev, "ev_prev", torch.float64, (8,), dev)
+    need = _chain_ws(n, ws, dev)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_md_step_chained(
+        ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, _ptr(x),
+        _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), float(dt), float(mass), _ptr(v),
+        _ptr(x_next), 1 if open_next else 0, _ptr(F), _ptr(e_atom), int(half), _ptr(ev_prev),
+        _ptr(ws), need, _stream(dev)), "ljmd_md_step_chained")
+    return x_next
+
+
+def md_step_sums(n, half, ws, ev=None):
+    """ev[8] (E, W, KE) of the md_step_chained call that wrote half `half` of ws."""
+    dev = ws.device
+    if ev is None:
+        ev = torch.empty(8, dtype=torch.float64, device=dev)
+    _need(ev, "ev", torch.float64, (8,), dev)
+    need = _chain_ws(n, ws, dev)
+    _lib.check(_lib.load().ljmd_md_step_sums(int(n), int(half), _ptr(ws), need, _ptr(ev),
+                                             _stream(dev)), "ljmd_md_step_sums")
+    return ev
 
 
 def integrate(stage, dt, mass, L, x, v, F, ke=None, ws=None):

@@ -51,6 +51,7 @@ def test_workspace_sizes(lib):
     assert W(lib.OP_SPH, 1000, 0, 1) >= 32 * 1000
     assert W(lib.OP_EWALD_REAL, 1000, 0, 1) >= 32 * 1000
     assert W(lib.OP_SPME, 1000, 64 ** 3, 1) >= 16 * 64 ** 3
+    assert W(lib.OP_MD_CHAIN, 500000, 0, 1) == 2 * W(lib.OP_FORCES, 500000, 0, 1)
     assert W(99, 10, 10, 1) == 0
 
 
@@ -102,6 +103,20 @@ def test_validation_rejects_bad_arguments(lib):
     assert call(lib, "ljmd_compute_forces", *args(0, 0, 2.5, 2, None)) == lib.EINVAL
     assert call(lib, "ljmd_compute_forces", *args(0, 0, 0.0, 1, None)) == lib.EINVAL
     assert call(lib, "ljmd_compute_forces", *args(0, 3, 2.5, 1, None)) == lib.EINVAL
+    # chained step: half outside {0, 1}, workspace of one half only, bad open_next;
+    # its sums: NULL ev, bad half, small workspace
+    fake2 = ctypes.c_void_p(32)
+    one = lib.load().ljmd_workspace_bytes(lib.OP_FORCES, 1000, 0, 1)
+    margs = lambda half, ws_bytes, open_next=1: (bb, 0, 2.5, 1, fake, fake, 1000, fake, None,
+                                                 fake, fake, 8, 0.005, 1.0, fake, fake2,
+                                                 open_next, None, None, half, None, fake,
+                                                 ws_bytes, None)
+    assert call(lib, "ljmd_md_step_chained", *margs(2, 2 * one)) == lib.EINVAL
+    assert call(lib, "ljmd_md_step_chained", *margs(0, one)) == lib.EWORKSPACE
+    assert call(lib, "ljmd_md_step_chained", *margs(1, 2 * one, open_next=3)) == lib.EINVAL
+    assert call(lib, "ljmd_md_step_sums", 1000, 0, fake, 2 * one, None, None) == lib.EINVAL
+    assert call(lib, "ljmd_md_step_sums", 1000, -1, fake, 2 * one, fake, None) == lib.EINVAL
+    assert call(lib, "ljmd_md_step_sums", 1000, 1, fake, one, fake, None) == lib.EWORKSPACE
     # energy requested without workspace
     assert call(lib, "ljmd_compute_forces", bb, 0, 0, 2.5, 1, fake, fake, 10, fake, None, fake,
                 fake, 8, fake, fake, fake, None, 0, None) == lib.EWORKSPACE

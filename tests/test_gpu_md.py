@@ -82,6 +82,84 @@ def test_md_step_matches_separate_calls(dev, prec, ntypes):
         assert torch.equal(v3, v4)
 
 
+@pytest.mark.parametrize("cells", [0, 1, 5, 10])
+def test_chained_steps_match_md_step(dev, cells):
+    """A run of ljmd_md_step_chained calls (halves 0, 1, 0, ...) gives bitwise the
+    positions, velocities and forces of ljmd_md_step; ljmd_md_step_sums of each half
+    is bitwise the inline ev, and the sums a chained launch forms for the previous
+    step agree with it to rounding.  cells 0 and 1 are the empty and one-atom boxes;
+    5 and 10 the fcc lattices of 500 and 4000 atoms (ragged last blocks)."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    if cells >= 2:
+        w = li.Workload("t", 4, cells=cells)
+        sys_ = li.make_system(w)
+        L, x, v = w.box, sys_["x"], sys_["v"]
+    else:
+        L = np.array([9.0, 10.0, 11.0])
+        x = np.array([[1.0, 2.0, 3.0]])[:cells]
+        v = np.array([[0.3, -0.2, 0.1]])[:cells]
+    n = x.shape[0]
+    xt = torch.as_tensor(x, dtype=torch.float64, device=dev).reshape(n, 3).contiguous()
+    types = torch.zeros(n, dtype=torch.int32, device=dev)
+    if n:
+        xs, _, _, _, cs = ops.bin(L, 2.8, xt)
+        nl = md.NeighborList(L, 2.8, ops.FULL, device=dev).build(xs, cs)
+        nbr, nnbr, maxn = nl.nbr, nl.nnbr, nl.maxn
+        vt = torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous()
+    else:
+        xs, vt = xt, torch.zeros((0, 3), dtype=torch.float64, device=dev)
+        nbr = torch.zeros(64 * 8, dtype=torch.int32, device=dev)
+        nnbr, maxn = torch.zeros(0, dtype=torch.int32, device=dev), 8
+    one = torch.ones(1, dtype=torch.float64, device=dev)
+    args = lambda xx: (L, ops.MIXED, 2.5, one, one, xx, types, nbr, nnbr, maxn, 0.005, 1.0)
+    ws = torch.empty(max(ops.workspace_bytes(ops.OP_MD_CHAIN, n), 8), dtype=torch.uint8,
+                     device=dev)
+    xa, va, xb, vb = xs.clone(), vt.clone(), xs.clone(), vt.clone()
+    prev = None
+    for k in range(5):
+        Fa, Fb = torch.empty_like(xa), torch.empty_like(xb)
+        xa2, _, ev = ops.md_step(*args(xa), va, F=Fa)
+        ev_prev = torch.full((8,), float("nan"), dtype=torch.float64, device=dev)
+        xb2 = ops.md_step_chained(*args(xb), vb, k % 2, ws, F=Fb,
+                                  ev_prev=ev_prev if k else None)
+        assert torch.equal(xa2, xb2) and torch.equal(va, vb) and torch.equal(Fa, Fb)
+        if k:
+            scale = prev.abs().max().item()
+            assert (ev_prev - prev).abs().max().item() <= 1e-12 * scale
+        prev = ev.clone()
+        assert torch.equal(ops.md_step_sums(n, k % 2, ws), prev)  # this step's half
+        if n == 0:
+            assert float(prev.abs().max()) == 0.0
+        xa, xb = xa2, xb2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lj_sim_chained_matches_inline(dev, prec):
+    """LJSim stepping with chained launches (the default) gives bitwise the
+    trajectory and E, W, KE of one ljmd_md_step per step, across rebuilds, energy on
+    and off, and calls of one step."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    runs = []
+    for chain in (False, True):
+        sim = md.LJSim(w.box, precision=P, device=dev)
+        sim.load(s["x"], s["v"])
+        out = []
+        for chunk, energy in ((1, True), (1, False), (2, True), (19, True), (41, False),
+                              (37, True)):
+            sim.step(chunk, energy=energy, chain=chain)
+            out.append((sim.x.clone(), sim.v.clone(), sim.F.clone(), sim.ev.clone(),
+                        sim.e_atom.clone() if energy else None))
+        runs.append(out)
+    for a, b in zip(*runs):
+        for ta, tb in zip(a, b):
+            assert (ta is None and tb is None) or torch.equal(ta, tb)
+
+
 def test_nve_lj256_matches_oracle_trajectory(dev, orc):
     """100 FP64 steps with rebuilds every 20: GPU and oracle Verlet-mirror trajectories agree."""
     from paper_2109_09056_amd import md, ops
