@@ -4,8 +4,9 @@
 A step is one velocity-Verlet MD step of the whole path: the binned re-sort
 and Verlet-list rebuild every 20 steps, LJ forces with per-atom energy,
 energy and virial, the closing half kick with the kinetic energy and the
-next step's opening half kick, drift and wrap (one fused launch on the full
-list plus one reduction launch).  Workload: the 500,000-atom dense LJ liquid (fcc 50^3 cells
+next step's opening half kick, drift and wrap: one fused launch per step on
+the full list, which also sums the previous step's energy/virial/KE partial
+rows, and one reduction launch closing the run.  Workload: the 500,000-atom dense LJ liquid (fcc 50^3 cells
 at rho* = 0.8442, T* = 1.44, rc 2.5, skin 0.3, dt 0.005), synthetic and
 seeded, inputs resident in HBM before the timed region.
 
@@ -31,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
 # HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
 # gives the two counters); set to None whenever the kernel changes until re-measured.
-FORCE_TRAFFIC = 232.55e6
-FORCE_VALU_BUSY = 0.546
-FORCE_TA_BUSY = 0.766
+FORCE_TRAFFIC = 232.89e6
+FORCE_VALU_BUSY = 0.542
+FORCE_TA_BUSY = 0.769
 
 
 def log(msg):
@@ -498,7 +499,7 @@ def main():
                    "mean_list_length": round(nbar, 3), "maxn": sim.nl.maxn},
         "roofline": {"bound": "hbm",
                      "kernel": "k_force_full<mixed, step, team 2> fused force+integration "
-                               "(+ energy/virial/KE column sum)",
+                               "(block 0 also sums the previous step's energy/virial/KE rows)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(FORCE_TRAFFIC) if FORCE_TRAFFIC else None,
