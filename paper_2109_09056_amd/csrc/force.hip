@@ -20,7 +20,8 @@
 // the result is bitwise reproducible.  HALF list: the owner adds s*d to F_i in
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
-// column-sum launch (deterministic).  Full lists take the virial as
+// column-sum launch (deterministic); in chained steps the first workgroup of
+// the next step's launch sums them instead.  Full lists take the virial as
 // sum_i x_i (x) F_i plus the pairs that cross a box face (add_pair).
 #include <type_traits>
 
