@@ -295,10 +295,17 @@ __global__ __launch_bounds__(kThreads * TEAM) void k_vjp(BwdArgs a) {
   }
 }
 
+// The parameter gradients from the VJP's partial rows, in one launch: the
+// column sums G[w][a][b] (w = 0: eps, 1: sigma) of the rows, then
 // geps[p] (+)= G[0][a][b] + G[0][b][a] (a != b) or G[0][a][a]; gsig likewise.
-__global__ void k_param_finalize(int32_t T, const double *__restrict__ colsums,
-                                 double *__restrict__ geps, double *__restrict__ gsig,
-                                 int accumulate) {
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_param_grad(int64_t rows, int stride, int32_t T,
+                                                       const double *__restrict__ partial,
+                                                       double *__restrict__ geps,
+                                                       double *__restrict__ gsig,
+                                                       int accumulate) {
+  __shared__ double part[THREADS];
+  colsum_lds<THREADS>(rows, stride, partial, part);
   const int P = T * (T + 1) / 2;
   const int q = threadIdx.x;
   if (q >= 2 * P) return;
@@ -309,8 +316,8 @@ __global__ void k_param_finalize(int32_t T, const double *__restrict__ colsums,
     ++aa;
   }
   const int bb = aa + rem;
-  double v = colsums[w * T * T + aa * T + bb];
-  if (aa != bb) v += colsums[w * T * T + bb * T + aa];
+  double v = part[w * T * T + aa * T + bb];
+  if (aa != bb) v += part[w * T * T + bb * T + aa];
   double *o = w == 0 ? geps : gsig;
   o[p] = accumulate ? o[p] + v : v;
 }
@@ -329,7 +336,7 @@ static int partial_stride(int32_t ntypes) {
 }
 
 size_t bwd_workspace(int64_t n, int32_t ntypes) {
-  return ((size_t)bwd_blocks(n) + 1) * partial_stride(ntypes) * sizeof(double);
+  return (size_t)bwd_blocks(n) * partial_stride(ntypes) * sizeof(double);
 }
 
 int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
@@ -356,9 +363,7 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
   a.stride = partial_stride(ntypes);
   a.partial = (double *)ws;
   const unsigned nblk = bwd_blocks(n);
-  const int cols = 2 * ntypes * ntypes;
   const int stride = a.stride;
-  double *colsums = a.partial + (size_t)nblk * stride;
   const bool mixed = precision == LJMD_MIXED;
 #define LJMD_VJP(M, TT, TEAM)                                                \
   do {                                                                       \
@@ -375,8 +380,7 @@ int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, con
     if (mixed) LJMD_VJP(true, 0, 1); else LJMD_VJP(false, 0, 1);
   }
 #undef LJMD_VJP
-  k_colsum<1024><<<1, 1024, 0, st>>>(nblk, stride, cols, a.partial, colsums, 1.0, 0);
-  k_param_finalize<<<1, 128, 0, st>>>(ntypes, colsums, geps, gsig, accumulate);
+  k_param_grad<1024><<<1, 1024, 0, st>>>(nblk, stride, ntypes, a.partial, geps, gsig, accumulate);
   return check_launch("ljmd_force_backward");
 }
 

@@ -111,17 +111,15 @@ __device__ __forceinline__ void block_sum(const double (&v)[NV], double *red, do
 }
 
 // Column sums over `rows` partial rows of `stride` doubles (stride a power of
-// two dividing THREADS), one block:  out[q] = scale * sum_r p[r*stride + q] for
-// q < ncols (+= when accumulate).  Thread t reads the flat array at t,
-// t + THREADS, ... (coalesced), so it always sees column t % stride; the
-// THREADS/stride threads of a column are then added by a tree in LDS.  Fixed
-// order throughout.
+// two dividing THREADS) by one block of THREADS threads, left in LDS:
+// part[q] = sum_r p[r*stride + q] for q < stride.  Thread t reads the flat
+// array at t, t + THREADS, ... (coalesced), so it always sees column
+// t % stride; the THREADS/stride threads of a column are then added by a tree
+// in `part` (THREADS doubles of LDS).  Fixed order throughout; every thread of
+// the block calls it and part[0..stride) is visible to all of them on return.
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, int ncols,
-                                                   const double *__restrict__ p,
-                                                   double *__restrict__ out, double scale,
-                                                   int accumulate) {
-  __shared__ double part[THREADS];
+__device__ __forceinline__ void colsum_lds(int64_t rows, int stride, const double *__restrict__ p,
+                                           double *part) {
   const int t = threadIdx.x;
   double s = 0.0;
   const int64_t total = rows * stride;
@@ -142,6 +140,18 @@ __global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, in
     if (t < off) part[t] += part[t + off];
     __syncthreads();
   }
+}
+
+// One launch of colsum_lds: out[q] = scale * column q for q < ncols (+= when
+// accumulate).
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_colsum(int64_t rows, int stride, int ncols,
+                                                   const double *__restrict__ p,
+                                                   double *__restrict__ out, double scale,
+                                                   int accumulate) {
+  __shared__ double part[THREADS];
+  colsum_lds<THREADS>(rows, stride, p, part);
+  const int t = threadIdx.x;
   if (t < ncols) out[t] = accumulate ? out[t] + scale * part[t] : scale * part[t];
 }
 
