@@ -312,9 +312,14 @@ def spme_bench(dev, reps=30):
     half -1): Ewald real space over the MD list (rc 2.5, alpha 1.2) and the SPME
     reciprocal part (order-4 B-splines, 128^3 grid), each timed alone with HIP events.
     Algorithmic bytes: real space per particle 4 nbar + 4 + 32 (own record) + 24 (F)
-    + 56 (packing x, q into records); reciprocal per grid point 16 (zero) + 6 x 32
-    (three FFT passes each way, read + write) + 32 (influence), per particle 32 (x, q)
-    + 24 (F) + 2 x 64 x 8 (spread and gather of n^3 = 64 points; atomics counted once)."""
+    + 56 (packing x, q into records); reciprocal: the real grid (8 B per point) is
+    zeroed, spread into, read by the x transform, written by the inverse x transform
+    and read by the gather (5 passes); the half grid (16 B per point, K0/2 + 1
+    columns) is written by the x transform, read and written by the y transform
+    each way and by the fused z / influence / inverse z pass, and read by the
+    inverse x transform (8 passes); per particle 32 (x, q for spreading) + 32 (for
+    the gather) + 48 (F read and written).  Interpolation points are not counted:
+    the spread and gather revisit grid points in cache."""
     import torch
     import lj_inputs as li
     from paper_2109_09056_amd import md, ops
@@ -342,7 +347,8 @@ def spme_bench(dev, reps=30):
     nb = float(nl.nnbr.double().mean().item())
     npts = K[0] * K[1] * K[2]
     br = n * (4.0 * nb + 116)
-    bk = npts * (16 + 6 * 32 + 32) + n * (56 + 2 * 64 * 8)
+    hpts = (K[0] // 2 + 1) * K[1] * K[2]
+    bk = 5 * 8 * npts + 8 * 16 * hpts + n * (32 + 32 + 48)
     return {"natoms": n, "grid": list(K), "order": order, "alpha": alpha, "rc": w.rc,
             "real_us": round(tr * 1e3, 2), "recip_us": round(tk * 1e3, 2),
             "both_us": round(tb * 1e3, 2),

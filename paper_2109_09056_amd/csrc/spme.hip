@@ -532,39 +532,73 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_c2r(const double2 *h, double
   }
 }
 
-// F(Q)(m) *= B(m) C(m); per block 1/2 sum B C |F(Q)|^2 (fixed order).  Each
-// thread takes kInfPerThread points (a block-stride apart), which keeps the
-// number of energy partials, and so the column sum after it, small.
-constexpr int kInfPerThread = 8;
-
-__global__ __launch_bounds__(kThreads) void k_influence(RecArgs a) {
+// z pass with the influence function between its two transforms: the rows of
+// the z pass of k_fft_yz (row r = m0 + W m1, element m2 at r + m2 W K1) are
+// transformed forward, multiplied by G(m) = B(m) C(m), transformed back, all in
+// LDS, so the half grid makes one round trip instead of three.  Per block the
+// reciprocal energy 1/2 sum G |F(Q)|^2 (fixed order).
+template <int NP>
+__global__ __launch_bounds__(kThreads) void k_fft_z_influence(RecArgs a, int64_t rows) {
+  constexpr int R = fft_rows<NP>();
+  __shared__ double2 buf[R * NP];
+  __shared__ double2 inv[R * NP];
+  __shared__ double2 twf[NP / 2 + 1];
+  __shared__ double2 twi[NP / 2 + 1];
   __shared__ double red[kThreads / kWave];
+  fill_twiddles<NP, 1>(twf, -1.0);
+  fill_twiddles<NP, 1>(twi, 1.0);
   const int W = a.K[0] / 2 + 1;
-  const int64_t npts = (int64_t)W * a.K[1] * a.K[2];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int64_t plane = (int64_t)W * a.K[1];
+  double2 *g = a.half;
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = idx % R, k = idx / R;
+    const int64_t r = r0 + m;
+    buf[m * NP + bitrev<NP>(k)] = r < rows ? g[r + k * plane] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_stages<NP, R, 1>(buf, twf);
   const double V = a.b.L[0] * a.b.L[1] * a.b.L[2];
   double v[1] = {0.0};
-  for (int r = 0; r < kInfPerThread; ++r) {
-    const int64_t p = ((int64_t)blockIdx.x * kInfPerThread + r) * blockDim.x + threadIdx.x;
-    if (p >= npts) break;
-    const int m0 = (int)(p % W);
-    const int m1 = (int)((p / W) % a.K[1]);
-    const int m2 = (int)(p / ((int64_t)W * a.K[1]));
-    const double f0 = m0 * a.b.invL[0];
-    const double f1 = (m1 <= a.K[1] / 2 ? m1 : m1 - a.K[1]) * a.b.invL[1];
-    const double f2 = (m2 <= a.K[2] / 2 ? m2 : m2 - a.K[2]) * a.b.invL[2];
-    const double msq = (f0 * f0 + f1 * f1) + f2 * f2;
-    double G = 0.0;
-    if (p != 0) {
-      const double C = exp(-kPi * kPi * msq / (a.alpha * a.alpha)) / (kPi * V * msq);
-      G = C * a.bmod[m0] * a.bmod[kMaxGrid + m1] * a.bmod[2 * kMaxGrid + m2];
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = idx / NP, m2 = idx % NP;
+    const int64_t r = r0 + m;
+    double2 out = make_double2(0.0, 0.0);
+    if (r < rows) {
+      const int m0 = (int)(r % W);
+      const int m1 = (int)(r / W);
+      const double f0 = m0 * a.b.invL[0];
+      const double f1 = (m1 <= a.K[1] / 2 ? m1 : m1 - a.K[1]) * a.b.invL[1];
+      const double f2 = (m2 <= a.K[2] / 2 ? m2 : m2 - a.K[2]) * a.b.invL[2];
+      const double msq = (f0 * f0 + f1 * f1) + f2 * f2;
+      double G = 0.0;
+      if (r != 0 || m2 != 0) {
+        const double C = exp(-kPi * kPi * msq / (a.alpha * a.alpha)) / (kPi * V * msq);
+        G = C * a.bmod[m0] * a.bmod[kMaxGrid + m1] * a.bmod[2 * kMaxGrid + m2];
+      }
+      const double2 z = buf[m * NP + m2];
+      // 1/2 G |F|^2, doubled for the columns 0 < m0 < K0/2 whose mirror -m0 is not stored
+      const double mult = (m0 == 0 || 2 * m0 == a.K[0]) ? 0.5 : 1.0;
+      v[0] += mult * G * (z.x * z.x + z.y * z.y);
+      out = make_double2(G * z.x, G * z.y);
     }
-    const double2 z = a.half[p];
-    // 1/2 G |F|^2, doubled for the columns 0 < m0 < K0/2 whose mirror -m0 is not stored
-    const double mult = (m0 == 0 || 2 * m0 == a.K[0]) ? 0.5 : 1.0;
-    v[0] += mult * G * (z.x * z.x + z.y * z.y);
-    a.half[p] = make_double2(G * z.x, G * z.y);
+    inv[m * NP + bitrev<NP>(m2)] = out;
+  }
+  __syncthreads();
+  fft_stages<NP, R, 1>(inv, twi);
+  for (int idx = threadIdx.x; idx < R * NP; idx += kThreads) {
+    const int m = idx % R, k = idx / R;
+    const int64_t r = r0 + m;
+    if (r < rows) g[r + k * plane] = inv[m * NP + k];
   }
   block_sum<kThreads / kWave, 1>(v, red, a.partial + blockIdx.x);
+}
+
+// Blocks of k_fft_z_influence (one energy partial each) for grid K.
+unsigned z_influence_blocks(const int32_t K[3]) {
+  const int R = 1024 / K[2] < 64 ? 1024 / K[2] : 64;  // fft_rows<K[2]>()
+  const int64_t rows = (int64_t)(K[0] / 2 + 1) * K[1];
+  return (unsigned)((rows + R - 1) / R);
 }
 
 // F_i = -q_i grad sum_k theta_i(k) phi(k); per block the self energy -alpha/sqrt(pi) q_i^2
@@ -627,6 +661,23 @@ void yz_pass(double2 *h, int axis, const int32_t K[3], double sign, hipStream_t 
   k_fft_yz<NP><<<(unsigned)((rows + R - 1) / R), kThreads, 0, st>>>(h, axis, W, K[1], rows, sign);
 }
 
+template <int NP>
+void z_influence_pass(const RecArgs &a, hipStream_t st) {
+  const int64_t rows = (int64_t)(a.K[0] / 2 + 1) * a.K[1];
+  k_fft_z_influence<NP><<<z_influence_blocks(a.K), kThreads, 0, st>>>(a, rows);
+}
+
+void fft_z_influence(const RecArgs &a, hipStream_t st) {
+  switch (a.K[2]) {
+    case 8: z_influence_pass<8>(a, st); break;
+    case 16: z_influence_pass<16>(a, st); break;
+    case 32: z_influence_pass<32>(a, st); break;
+    case 64: z_influence_pass<64>(a, st); break;
+    case 128: z_influence_pass<128>(a, st); break;
+    default: z_influence_pass<256>(a, st); break;
+  }
+}
+
 void fft_yz(double2 *h, int axis, const int32_t K[3], double sign, hipStream_t st) {
   switch (K[axis]) {
     case 8: yz_pass<8>(h, axis, K, sign, st); break;
@@ -661,7 +712,6 @@ void fft_x(double *g, double2 *h, const int32_t K[3], bool forward, hipStream_t 
 }
 
 int64_t grid_points(const int32_t K[3]) { return (int64_t)K[0] * K[1] * K[2]; }
-int64_t half_points(const int32_t K[3]) { return (int64_t)(K[0] / 2 + 1) * K[1] * K[2]; }
 unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per > 0 ? (n + per - 1) / per : 1); }
 
 template <int N>
@@ -672,9 +722,7 @@ void launch_rec_order(const RecArgs &a, double *self_partial, hipStream_t st) {
   if (a.n > 0) k_spread<N><<<blocks_of(a.n, kWave), kWave, 0, st>>>(a);
   fft_x(a.grid, a.half, a.K, true, st);
   fft_yz(a.half, 1, a.K, -1.0, st);
-  fft_yz(a.half, 2, a.K, -1.0, st);
-  k_influence<<<blocks_of(half_points(a.K), kThreads * kInfPerThread), kThreads, 0, st>>>(a);
-  fft_yz(a.half, 2, a.K, 1.0, st);
+  fft_z_influence(a, st);
   fft_yz(a.half, 1, a.K, 1.0, st);
   fft_x(a.grid, a.half, a.K, false, st);
   if (a.n > 0) k_gather<N><<<blocks_of(a.n, kThreads), kThreads, 0, st>>>(a, self_partial);
@@ -687,13 +735,13 @@ size_t ewald_real_workspace(int64_t n) {
          (size_t)blocks_of(n, kEwAtoms) * sizeof(double) + kErfcTable * sizeof(double) + 256;
 }
 
-// real grid, half grid (at most npts/2 + npts/8 complex points: K0 >= 8), tables, partials
+// real grid, half grid (at most npts/2 + npts/8 complex points: K0 >= 8), tables,
+// partials (the z/influence pass keeps at least 512 half-grid points per block)
 size_t spme_workspace(int64_t n, int64_t npts) {
   const int64_t half = npts / 2 + npts / 8;
   return (size_t)npts * sizeof(double) + (size_t)half * sizeof(double2) +
          3 * kMaxGrid * sizeof(double) +
-         ((size_t)blocks_of(half, kThreads * kInfPerThread) + blocks_of(n, kThreads)) *
-             sizeof(double) + 256;
+         ((size_t)blocks_of(half, 512) + blocks_of(n, kThreads)) * sizeof(double) + 256;
 }
 
 int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const double *x,
@@ -761,7 +809,7 @@ int launch_spme_recip(const BoxK &b, double alpha, int32_t order, const int32_t 
   a.bmod = (double *)p;
   p += 3 * kMaxGrid * sizeof(double);
   a.partial = (double *)p;
-  const unsigned ninf = blocks_of(half_points(K), kThreads * kInfPerThread);
+  const unsigned ninf = z_influence_blocks(K);
   const unsigned ngat = blocks_of(n, kThreads);
   double *self_partial = n > 0 ? a.partial + ninf : nullptr;
   switch (order) {
