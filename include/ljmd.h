@@ -22,7 +22,7 @@
  *   ljmd_list_to_csr, ljmd_compute_forces_csr
  *                         compressed list form and team-per-atom traversal
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
- *   ljmd_sph_density, ljmd_sph_accel
+ *   ljmd_sph_density, ljmd_sph_accel, ljmd_sph_accel_step
  *                         SPH density summation and pressure acceleration over
  *                         the same lists (second short-range pair kernel)
  * *   ljmd_ewald_real, ljmd_spme_recip
@@ -89,7 +89,7 @@ extern "C" {
 #define LJMD_OP_LOSS 4
 #define LJMD_OP_CSR 5        /* ljmd_list_to_csr */
 #define LJMD_OP_FORCES_CSR 6 /* ljmd_compute_forces_csr (any team) */
-#define LJMD_OP_SPH 7        /* ljmd_sph_density (with u_total), ljmd_sph_accel */
+#define LJMD_OP_SPH 7        /* ljmd_sph_density (with u_total), ljmd_sph_accel(_step) */
 #define LJMD_OP_EWALD_REAL 8 /* ljmd_ewald_real */
 #define LJMD_OP_SPME 9       /* ljmd_spme_recip; ncells = K[0]*K[1]*K[2] grid points */
 #define LJMD_OP_MD_CHAIN 10  /* ljmd_md_step_chained, ljmd_md_step_sums (two halves) */
@@ -367,6 +367,25 @@ int ljmd_sph_density(const ljmd_box *box, double h, double mass, double c0, doub
 int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,
                    const double *x, const double *rho, const int32_t *nbr, const int32_t *nnbr,
                    int32_t maxn, double *acc, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_sph_accel_step -- ljmd_sph_accel followed, in the same pass, by the
+ * closing half kick of this step and the next step's opening half kick, drift
+ * and wrap (velocity Verlet with the acceleration as F/m): per component
+ * v += dt/2 a twice, x += dt v, wrapped into [0, L).  x, v and acc are bitwise
+ * those of ljmd_sph_accel then ljmd_integrate(LJMD_KICK_KICK_DRIFT, dt,
+ * mass 1, F = acc) (the paper's MD timestep: forces, then propagation --
+ * Introduction).
+ *   x     [n][3] in/out: positions of this step in, of the next step out
+ *   v     [n][3] in/out: half-step velocities
+ *   dt    nonzero, finite
+ *   acc   [n][3] output of a_i, or NULL
+ * Other arguments as in ljmd_sph_accel.
+ */
+int ljmd_sph_accel_step(const ljmd_box *box, double h, double mass, double c0, double rho0,
+                        int64_t n, double *x, double *v, const double *rho, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, double dt, double *acc, void *ws,
+                        size_t ws_bytes, void *stream);
 
 /*
  * ljmd_ewald_real, ljmd_spme_recip -- electrostatics of point charges by smooth

@@ -62,6 +62,8 @@ SIGNATURES = {
                                 _p, _sz, _p]),
     "ljmd_sph_accel": (_int, [_box, _dbl, _dbl, _dbl, _dbl, _i64, _p, _p, _p, _p, _i32, _p, _p,
                               _sz, _p]),
+    "ljmd_sph_accel_step": (_int, [_box, _dbl, _dbl, _dbl, _dbl, _i64, _p, _p, _p, _p, _p, _i32,
+                                   _dbl, _p, _p, _sz, _p]),
     "ljmd_ewald_real": (_int, [_box, _dbl, _dbl, _i64, _p, _p, _p, _p, _i32, _p, _p, _int, _p,
                                _sz, _p]),
     "ljmd_spme_recip": (_int, [_box, _dbl, _i32, ctypes.POINTER(_i32), _i64, _p, _p, _p, _p,

@@ -47,7 +47,8 @@ int launch_sph_density(const BoxK &b, double h, double mass, double c0, double r
                        double *rho, double *u_total, void *ws, hipStream_t st);
 int launch_sph_accel(const BoxK &b, double h, double mass, double c0, double rho0, int64_t n,
                      const double *x, const double *rho, const int32_t *nbr,
-                     const int32_t *nnbr, int32_t maxn, double *acc, void *ws, hipStream_t st);
+                     const int32_t *nnbr, int32_t maxn, double *acc, double dt, double *v,
+                     double *x_out, void *ws, hipStream_t st);
 size_t ewald_real_workspace(int64_t n);
 size_t spme_workspace(int64_t n, int64_t npts);
 int launch_ewald_real(const BoxK &b, double alpha, double rc, int64_t n, const double *x,
@@ -321,8 +322,22 @@ int ljmd_sph_accel(const ljmd_box *box, double h, double mass, double c0, double
   LJMD_TRY(check_ws(ws, ws_bytes, n > 0 ? sph_workspace(n) : 0));
   if (n > 0 && ((uintptr_t)ws & 31u) != 0)
     return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
-  return launch_sph_accel(make_box(box), h, mass, c0, rho0, n, x, rho, nbr, nnbr, maxn, acc, ws,
-                          (hipStream_t)stream);
+  return launch_sph_accel(make_box(box), h, mass, c0, rho0, n, x, rho, nbr, nnbr, maxn, acc, 0.0,
+                          nullptr, nullptr, ws, (hipStream_t)stream);
+}
+
+int ljmd_sph_accel_step(const ljmd_box *box, double h, double mass, double c0, double rho0,
+                        int64_t n, double *x, double *v, const double *rho, const int32_t *nbr,
+                        const int32_t *nnbr, int32_t maxn, double dt, double *acc, void *ws,
+                        size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_sph(box, h, mass, c0, rho0, n, x, nbr, nnbr, maxn));
+  if (n > 0 && (!rho || !v)) return set_error(LJMD_EINVAL, "rho/v is NULL");
+  if (!isfinite(dt) || dt == 0.0) return set_error(LJMD_EINVAL, "dt = %g", dt);
+  LJMD_TRY(check_ws(ws, ws_bytes, n > 0 ? sph_workspace(n) : 0));
+  if (n > 0 && ((uintptr_t)ws & 31u) != 0)
+    return set_error(LJMD_EINVAL, "ws must be aligned to 32 bytes");
+  return launch_sph_accel(make_box(box), h, mass, c0, rho0, n, x, rho, nbr, nnbr, maxn, acc, dt,
+                          n > 0 ? v : nullptr, x, ws, (hipStream_t)stream);
 }
 
 int ljmd_ewald_real(const ljmd_box *box, double alpha, double rc, int64_t n, const double *x,

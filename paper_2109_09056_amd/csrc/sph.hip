@@ -49,6 +49,9 @@ struct SphArgs {
   double *partial;         // density pass: per-block internal energy
   const double4 *xp;       // acceleration pass: packed (x, y, z, P)
   double *acc;
+  // acceleration pass with the integration step (k_sph_accel<..., true>)
+  double *v, *x_out;
+  double dt, hdt;
 };
 
 template <bool WIDE>
@@ -264,7 +267,10 @@ __device__ __forceinline__ void accel_row(const SphArgs &a, const int32_t *row, 
   }
 }
 
-template <bool WIDE>
+// STEP: after the acceleration, the closing half kick of this step and the next
+// step's opening half kick and drift with wrap, per component exactly as the
+// integrator's fused kick-kick-drift (unit mass: the acceleration is F/m).
+template <bool WIDE, bool STEP>
 __global__ __launch_bounds__(kSphThreads) void k_sph_accel(SphArgs a) {
   const int t = (int)threadIdx.x % kSphTeam;
   const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kSphAtoms + (int)threadIdx.x / kSphTeam;
@@ -290,9 +296,28 @@ __global__ __launch_bounds__(kSphThreads) void k_sph_accel(SphArgs a) {
   ay += __shfl_xor(ay, 1, kWave);
   az += __shfl_xor(az, 1, kWave);
   if (live && t == 0) {
-    a.acc[3 * (int64_t)i] = -a.gnorm * ax;
-    a.acc[3 * (int64_t)i + 1] = -a.gnorm * ay;
-    a.acc[3 * (int64_t)i + 2] = -a.gnorm * az;
+    const double f[3] = {-a.gnorm * ax, -a.gnorm * ay, -a.gnorm * az};
+    if (!STEP || a.acc) {
+      a.acc[3 * (int64_t)i] = f[0];
+      a.acc[3 * (int64_t)i + 1] = f[1];
+      a.acc[3 * (int64_t)i + 2] = f[2];
+    }
+    if constexpr (STEP) {
+      const double xo[3] = {me.x, me.y, me.z};  // the packed copy of x_i
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t q = 3 * (int64_t)i + k;
+        const double L = a.b.L[k];
+        const double kick = a.hdt * f[k];
+        const double vh = (a.v[q] + kick) + kick;
+        double xq = xo[k] + a.dt * vh;
+        if (xq >= L) xq -= L;
+        else if (xq < 0.0) xq += L;
+        if (xq >= L) xq -= L;
+        a.v[q] = vh;
+        a.x_out[q] = xq;
+      }
+    }
   }
 }
 
@@ -351,20 +376,33 @@ int launch_sph_density(const BoxK &b, double h, double mass, double c0, double r
   return check_launch("ljmd_sph_density");
 }
 
+// v == NULL: the acceleration pass alone; otherwise also the kick-kick-drift of
+// the particles into x_out (= x: the pass reads positions from the packed copy).
 int launch_sph_accel(const BoxK &b, double h, double mass, double c0, double rho0, int64_t n,
                      const double *x, const double *rho, const int32_t *nbr,
-                     const int32_t *nnbr, int32_t maxn, double *acc, void *ws, hipStream_t st) {
+                     const int32_t *nnbr, int32_t maxn, double *acc, double dt, double *v,
+                     double *x_out, void *ws, hipStream_t st) {
   SphArgs a = make_args(b, h, mass, c0, rho0, n, x, nbr, nnbr, maxn);
   a.rho = const_cast<double *>(rho);  // read only in this pass
   a.xp = (const double4 *)ws;
   a.acc = acc;
+  a.v = v;
+  a.x_out = x_out;
+  a.dt = dt;
+  a.hdt = 0.5 * dt;
   if (n > 0) {
     k_sph_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, (double4 *)ws);
     const unsigned nblk = sph_blocks(n);
-    if (n > kNarrowAtoms) k_sph_accel<true><<<nblk, kSphThreads, 0, st>>>(a);
-    else k_sph_accel<false><<<nblk, kSphThreads, 0, st>>>(a);
+    const bool wide = n > kNarrowAtoms;
+    if (v) {
+      if (wide) k_sph_accel<true, true><<<nblk, kSphThreads, 0, st>>>(a);
+      else k_sph_accel<false, true><<<nblk, kSphThreads, 0, st>>>(a);
+    } else {
+      if (wide) k_sph_accel<true, false><<<nblk, kSphThreads, 0, st>>>(a);
+      else k_sph_accel<false, false><<<nblk, kSphThreads, 0, st>>>(a);
+    }
   }
-  return check_launch("ljmd_sph_accel");
+  return check_launch(v ? "ljmd_sph_accel_step" : "ljmd_sph_accel");
 }
 
 }  // namespace ljmd

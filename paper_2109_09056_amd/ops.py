@@ -465,6 +465,22 @@ def sph_accel(L, h, mass, c0, rho0, x, rho, nbr, nnbr, maxn, acc=None, ws=None):
     return acc
 
 
+def sph_accel_step(L, h, mass, c0, rho0, x, v, rho, nbr, nnbr, maxn, dt, acc=None, ws=None):
+    """sph_accel, then the closing and next opening half kicks and the drift with wrap,
+    in place on x and v (acc written only when given)."""
+    n, dev = _sph_list(x, nbr, nnbr, maxn)
+    _need(rho, "rho", torch.float64, (n,), dev)
+    _need(v, "v", torch.float64, (n, 3), dev)
+    _need(acc, "acc", torch.float64, (n, 3), dev)
+    ws, need = _ws(OP_SPH, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_sph_accel_step(
+        ctypes.byref(b), float(h), float(mass), float(c0), float(rho0), n, _ptr(x), _ptr(v),
+        _ptr(rho), _ptr(nbr), _ptr(nnbr), int(maxn), float(dt), _ptr(acc), _ptr(ws), need,
+        _stream(dev)), "ljmd_sph_accel_step")
+    return x, v
+
+
 def ewald_real(L, alpha, rc, x, q, nbr, nnbr, maxn, F=None, e_total=None, want_energy=False,
                accumulate=False, ws=None):
     """Ewald direct-space forces (and E_dir) over a FULL list with rlist >= rc."""

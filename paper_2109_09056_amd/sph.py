@@ -76,8 +76,11 @@ class SPHSim:
         ops.sph_accel(self.L, self.h, self.mass, self.c0, self.rho0, self.x, self.rho, nl.nbr,
                       nl.nnbr, nl.maxn, acc=self.acc, ws=self.ws)
 
-    def step(self, nsteps=1, energy=False):
-        """nsteps velocity-Verlet steps; with energy, U and the kinetic energy of the last."""
+    def step(self, nsteps=1, energy=False, fused=True):
+        """nsteps velocity-Verlet steps; with energy, U and the kinetic energy of the last.
+        fused: every step but the last runs its acceleration and integration as one
+        pass (ljmd_sph_accel_step; bitwise the separate calls).  acc holds the last
+        step's accelerations."""
         if nsteps <= 0:
             return self
         ops.integrate(KICK_DRIFT, self.dt, 1.0, self.L, self.x, self.v, self.acc)
@@ -86,11 +89,19 @@ class SPHSim:
             self.step_count += 1
             if self.step_count % self.rebuild_every == 0:
                 self.rebuild()
-            self.forces(energy=energy and last)
             if last:
+                self.forces(energy=energy)
                 ops.integrate(KICK, self.dt, 1.0, self.L, self.x, self.v, self.acc,
                               ke=self.ke if energy else None, ws=self.ws_int)
+            elif fused:
+                # acceleration, closing kick and the next opening kick + drift in one pass
+                nl = self.nl
+                ops.sph_density(self.L, self.h, self.mass, self.c0, self.rho0, self.x, nl.nbr,
+                                nl.nnbr, nl.maxn, rho=self.rho, ws=self.ws)
+                ops.sph_accel_step(self.L, self.h, self.mass, self.c0, self.rho0, self.x, self.v,
+                                   self.rho, nl.nbr, nl.nnbr, nl.maxn, self.dt, ws=self.ws)
             else:
+                self.forces()
                 ops.integrate(KICK_KICK_DRIFT, self.dt, 1.0, self.L, self.x, self.v, self.acc)
         return self
 

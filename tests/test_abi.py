@@ -117,6 +117,12 @@ def test_validation_rejects_bad_arguments(lib):
     assert call(lib, "ljmd_md_step_sums", 1000, 0, fake, 2 * one, None, None) == lib.EINVAL
     assert call(lib, "ljmd_md_step_sums", 1000, -1, fake, 2 * one, fake, None) == lib.EINVAL
     assert call(lib, "ljmd_md_step_sums", 1000, 1, fake, one, fake, None) == lib.EWORKSPACE
+    # SPH fused step: zero dt, missing velocities
+    sargs = lambda v, dt: (bb, 1.0, 1.0, 10.0, 1.0, 1000, fake, v, fake, fake, fake, 8, dt,
+                           None, fake, 1 << 20, None)
+    assert call(lib, "ljmd_sph_accel_step", *sargs(fake, 0.0)) == lib.EINVAL
+    assert call(lib, "ljmd_sph_accel_step", *sargs(fake, float("inf"))) == lib.EINVAL
+    assert call(lib, "ljmd_sph_accel_step", *sargs(None, 0.01)) == lib.EINVAL
     # energy requested without workspace
     assert call(lib, "ljmd_compute_forces", bb, 0, 0, 2.5, 1, fake, fake, 10, fake, None, fake,
                 fake, 8, fake, fake, fake, None, 0, None) == lib.EWORKSPACE
