@@ -237,12 +237,13 @@ class LJSim:
         """Advance nsteps velocity-Verlet steps; E, W and KE are produced every step
         (the per-atom energy only when energy is true).
 
-        FULL lists run one fused launch per step (ljmd_md_step); HALF lists run the
-        separate force and integration calls.  force_events: optional iterator with
-        one item per step, a pre-created (start, end) timing-event pair recorded
-        on the current stream around that step's force launch, or None.  graphs: replay the steps between two rebuilds
-        as one captured HIP graph (FULL lists, no timing events; bitwise the same
-        trajectory as launching them one by one).  on_positions: optional callable
+        FULL lists run one fused launch per step (ljmd_md_step_chained, or
+        ljmd_md_step without chain); HALF lists run the separate force and
+        integration calls.  force_events: optional iterator with one item per step,
+        a pre-created (start, end) timing-event pair recorded on the current stream
+        around that step's force launch, or None.  graphs: replay the steps between
+        two rebuilds as one captured HIP graph (FULL lists, no timing events; bitwise
+        the same trajectory as launching them one by one).  on_positions: optional callable
         given, for every step in order, the positions tensor the force call of that
         step reads (valid until the next launch on the stream; clone to keep it).
         chain: launched steps run as ljmd_md_step_chained, each summing the previous
@@ -257,8 +258,9 @@ class LJSim:
             return self._step_unfused(nsteps, energy, force_events, on_positions)
         integrate, mdstep = lib.ljmd_integrate, lib.ljmd_md_step
         use_graphs = graphs and force_events is None and on_positions is None
+        name = "ljmd_md_step"
         if chain and not use_graphs:
-            mdstep = lib.ljmd_md_step_chained
+            mdstep, name = lib.ljmd_md_step_chained, "ljmd_md_step_chained"
         else:
             chain = False
         half = None  # half of the chained workspace the previous launch wrote
@@ -289,10 +291,10 @@ class LJSim:
             ab = next(force_events) if force_events is not None else None
             if ab is not None:
                 ab[0].record()
-                _lib.check(mdstep(*args), "ljmd_md_step")
+                _lib.check(mdstep(*args), name)
                 ab[1].record()
             else:
-                _lib.check(mdstep(*args), "ljmd_md_step")
+                _lib.check(mdstep(*args), name)
             if chain and last:
                 ops.md_step_sums(self.n, half, self._ws[ops.OP_MD_CHAIN], ev=self.ev)
             if on_positions is not None:
