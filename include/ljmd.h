@@ -25,7 +25,7 @@
  *   ljmd_sph_density, ljmd_sph_accel, ljmd_sph_accel_step
  *                         SPH density summation and pressure acceleration over
  *                         the same lists (second short-range pair kernel)
- * *   ljmd_ewald_real, ljmd_spme_recip
+ *   ljmd_ewald_real, ljmd_spme_recip
  *                         long-range electrostatics: Ewald real space over the
  *                         lists, smooth particle-mesh Ewald in reciprocal space
  *
@@ -429,8 +429,9 @@ int ljmd_spme_recip(const ljmd_box *box, double alpha, int32_t order, const int3
  *
  * Reverse of one step (x_n, v_n) -> (x_{n+1}, v_{n+1}) once the VJP at
  * x_{n+1} has been folded into xbar:  vbar += dt * xbar, then the VJP at x_n
- * with cotangent w * dt * vbar (w = 1 where the two half kicks meeting at an
- * interior x_n are merged, 1/2 at the first step).
+ * with cotangent w * dt * vbar.  The kicks add dt/(2m) F, so w = 1/m where the
+ * two half kicks meeting at an interior x_n are merged and 1/(2m) at the
+ * first step.
  * ljmd_adjoint_kick: vbar += dt * xbar; g = w * dt * vbar.  [n][3] each. */
 int ljmd_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
                       double *g, void *stream);

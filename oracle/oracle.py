@@ -266,7 +266,7 @@ def run_nve(x, v, L, rc, rlist, dt, steps, rebuild_every=20, eps=(1.0,), sigma=(
 
 # ------------------------------------------------------- trajectory adjoint --
 
-def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None):
+def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None, mass=1.0):
     """Forward velocity Verlet with one list built at step 0 (steps <= rebuild cadence).
 
     Returns (xs, v_T, unwrapped x_T, lst): xs[k] is the wrapped position at step k.
@@ -278,21 +278,22 @@ def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None):
     F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
     xs = [x.copy()]
     for _ in range(steps):
-        kick_drift(x, v, F, dt, L, img=img)
+        kick_drift(x, v, F, dt, L, mass=mass, img=img)
         F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
-        kick(v, F, dt)
+        kick(v, F, dt, mass=mass)
         xs.append(x.copy())
     return xs, v, x + img * _box(L), lst
 
 
-def trajectory_adjoint(xs, L, rc, dt, eps, sigma, xbar_T, vbar_T, types=None, lst=None):
+def trajectory_adjoint(xs, L, rc, dt, eps, sigma, xbar_T, vbar_T, types=None, lst=None,
+                       mass=1.0):
     """Discrete adjoint of the velocity-Verlet trajectory, newest step first.
 
-    Step n maps (x_n, v_n) to (x_{n+1}, v_{n+1}) through h = v_n + dt/2 F(x_n),
-    x_{n+1} = x_n + dt h, v_{n+1} = h + dt/2 F(x_{n+1}).  Its reverse, with
+    Step n maps (x_n, v_n) to (x_{n+1}, v_{n+1}) through h = v_n + dt/(2m) F(x_n),
+    x_{n+1} = x_n + dt h, v_{n+1} = h + dt/(2m) F(x_{n+1}).  Its reverse, with
     J^T a the force VJP at the stated positions:
-        xbar_{n+1} += J^T(x_{n+1}) (dt/2 vbar_{n+1});  hbar = vbar_{n+1} + dt xbar_{n+1}
-        xbar_n = xbar_{n+1} + J^T(x_n) (dt/2 hbar);    vbar_n = hbar
+        xbar_{n+1} += J^T(x_{n+1}) (dt/(2m) vbar_{n+1});  hbar = vbar_{n+1} + dt xbar_{n+1}
+        xbar_n = xbar_{n+1} + J^T(x_n) (dt/(2m) hbar);    vbar_n = hbar
     Parameter cotangents collect the same VJP calls.  Returns
     (xbar_0, vbar_0, geps, gsigma).
     """
@@ -306,13 +307,14 @@ def trajectory_adjoint(xs, L, rc, dt, eps, sigma, xbar_T, vbar_T, types=None, ls
     def vjp(x, a):
         return force_vjp(x, L, rc, a, eps, sigma, types, off, nb)
 
+    c = 0.5 * dt / mass
     for n in range(T - 1, -1, -1):
-        gx, e1, s1 = vjp(xs[n + 1], 0.5 * dt * vbar)
+        gx, e1, s1 = vjp(xs[n + 1], c * vbar)
         xbar += gx
         ge += e1
         gs += s1
         hbar = vbar + dt * xbar
-        gx, e2, s2 = vjp(xs[n], 0.5 * dt * hbar)
+        gx, e2, s2 = vjp(xs[n], c * hbar)
         xbar = xbar + gx
         ge += e2
         gs += s2

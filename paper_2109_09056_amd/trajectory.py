@@ -11,7 +11,8 @@ trajectory exactly), then walked backwards; per step n (x_n -> x_{n+1})
     vbar += dt * xbar
     (xbar, pbar) += J^T(x_n) (w_n dt vbar)     w_n = 1 (n > 0), 1/2 (n = 0)
 where J^T is ljmd_force_backward: the two half-kick VJPs that meet at every
-interior x_n are merged into one call.  Gradients w.r.t. x_0, v_0 and the
+interior x_n are merged into one call.  With mass m the kicks add dt/(2m) F,
+so the cotangent handed to the VJP carries 1/m: w_n = 1/m (n > 0), 1/(2m) (n = 0).  Gradients w.r.t. x_0, v_0 and the
 packed (eps, sigma) come back in the caller's atom order.
 """
 from __future__ import annotations
@@ -97,8 +98,9 @@ def backprop_trajectory(L, x0, v0, types, eps, sigma, xref, steps=20, checkpoint
             ref = ckpt[e][0] if e in ckpt else xT
             recompute_ok &= bool(torch.equal(xs.pop(), ref))
         for n in range(e - 1, s - 1, -1):
-            _lib.check(lib.ljmd_adjoint_kick(sim.n, dt, 1.0 if n > 0 else 0.5, p(xbar), p(vbar),
-                                             p(g), stream), "ljmd_adjoint_kick")
+            wn = (1.0 if n > 0 else 0.5) / mass
+            _lib.check(lib.ljmd_adjoint_kick(sim.n, dt, wn, p(xbar), p(vbar), p(g), stream),
+                       "ljmd_adjoint_kick")
             _lib.check(lib.ljmd_force_backward(
                 ctypes.byref(box), precision, rc, sim.ntypes, p(sim.eps), p(sim.sigma), sim.n,
                 p(xs[n - s]), p(sim.types), p(nl.nbr), p(nl.nnbr), nl.maxn, p(g), p(xbar),

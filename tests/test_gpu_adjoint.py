@@ -138,22 +138,26 @@ def test_autograd_force_matching_loss(dev, orc, fm):
             assert grad == pytest.approx(fd, rel=1e-5)
 
 
-def test_trajectory_backprop_vs_oracle_small(dev, orc):
+@pytest.mark.parametrize("mass", [1.0, 2.0])
+def test_trajectory_backprop_vs_oracle_small(dev, orc, mass):
     """256 atoms, two types, 20 steps, checkpoints every 5, FP64: GPU gradient vs the
-    oracle's (uncheckpointed, unmerged) discrete adjoint."""
+    oracle's (uncheckpointed, unmerged) discrete adjoint; mass 2 checks the 1/m of the
+    kicks in the reverse pass."""
     from paper_2109_09056_amd import ops, trajectory
     w = li.Workload("traj_small", 4, cells=4, ntypes=2, steps=20, checkpoint_every=5)
     x0, v0, ty = li.positions(w), li.velocities(w), li.types(w)
     eps, sig = li.params(w)
     et, st = li.perturbed_params(w)
-    _, _, xref, _ = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, et, st, ty)
+    _, _, xref, _ = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, et, st, ty, mass=mass)
     r = trajectory.backprop_trajectory(w.box, x0, v0, ty, eps, sig, xref, steps=20,
-                                       checkpoint_every=5, precision=ops.FP64, device=dev)
+                                       checkpoint_every=5, mass=mass, precision=ops.FP64,
+                                       device=dev)
     assert r.recompute_bitwise
-    xs, vT, xT_unw, lst = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, eps, sig, ty)
+    xs, vT, xT_unw, lst = orc.trajectory(x0, v0, w.box, w.rc, w.rlist, w.dt, 20, eps, sig, ty,
+                                         mass=mass)
     d = xT_unw - xref
     gx0, gv0, ge, gs = orc.trajectory_adjoint(xs, w.box, w.rc, w.dt, eps, sig, d,
-                                              np.zeros_like(d), ty, lst)
+                                              np.zeros_like(d), ty, lst, mass=mass)
     assert float(r.loss.item()) == pytest.approx(0.5 * (d * d).sum(), rel=1e-9)
     assert max_rel_vec(r.gx0.cpu().numpy(), gx0) <= 1e-9
     assert max_rel_vec(r.gv0.cpu().numpy(), gv0) <= 1e-9

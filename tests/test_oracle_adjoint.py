@@ -107,21 +107,23 @@ def test_dot_product(orc):
     assert (Jv * wv).sum() == pytest.approx((v * gx).sum(), rel=1e-6)
 
 
-def traj_loss(orc, x0, v0, L, rc, rlist, dt, steps, eps, sig, types, xref):
-    xs, vT, xT, lst = orc.trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sig, types)
+def traj_loss(orc, x0, v0, L, rc, rlist, dt, steps, eps, sig, types, xref, mass=1.0):
+    xs, vT, xT, lst = orc.trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sig, types, mass=mass)
     d = xT - xref
     return 0.5 * (d * d).sum(), xs, d, lst
 
 
-def test_trajectory_adjoint_fd(orc):
+@pytest.mark.parametrize("mass", [1.0, 2.0])
+def test_trajectory_adjoint_fd(orc, mass):
+    """FD through 20 velocity-Verlet steps; mass 2 fixes where 1/m enters the adjoint."""
     tw, x0, types, eps, sig = system(index=4)
     L, rc, rl, dt, T = tw.box, tw.rc, tw.rlist, tw.dt, 20
     v0 = li.velocities(tw)
     et, st = li.perturbed_params(tw)
-    _, _, xref, _ = orc.trajectory(x0, v0, L, rc, rl, dt, T, et, st, types)
-    loss, xs, xbarT, lst = traj_loss(orc, x0, v0, L, rc, rl, dt, T, eps, sig, types, xref)
+    _, _, xref, _ = orc.trajectory(x0, v0, L, rc, rl, dt, T, et, st, types, mass=mass)
+    loss, xs, xbarT, lst = traj_loss(orc, x0, v0, L, rc, rl, dt, T, eps, sig, types, xref, mass)
     gx0, gv0, ge, gs = orc.trajectory_adjoint(xs, L, rc, dt, eps, sig, xbarT,
-                                              np.zeros_like(xbarT), types, lst)
+                                              np.zeros_like(xbarT), types, lst, mass=mass)
     rng = np.random.default_rng(1)
     h = 1e-6
     for _ in range(6):
@@ -131,11 +133,11 @@ def test_trajectory_adjoint_fd(orc):
             ap[i, k] += h
             am[i, k] -= h
             if arr is x0:
-                lp = traj_loss(orc, ap, v0, L, rc, rl, dt, T, eps, sig, types, xref)[0]
-                lm = traj_loss(orc, am, v0, L, rc, rl, dt, T, eps, sig, types, xref)[0]
+                lp = traj_loss(orc, ap, v0, L, rc, rl, dt, T, eps, sig, types, xref, mass)[0]
+                lm = traj_loss(orc, am, v0, L, rc, rl, dt, T, eps, sig, types, xref, mass)[0]
             else:
-                lp = traj_loss(orc, x0, ap, L, rc, rl, dt, T, eps, sig, types, xref)[0]
-                lm = traj_loss(orc, x0, am, L, rc, rl, dt, T, eps, sig, types, xref)[0]
+                lp = traj_loss(orc, x0, ap, L, rc, rl, dt, T, eps, sig, types, xref, mass)[0]
+                lm = traj_loss(orc, x0, am, L, rc, rl, dt, T, eps, sig, types, xref, mass)[0]
             assert grad[i, k] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-9)
     hp = 1e-7
     for p in range(eps.size):
@@ -144,6 +146,6 @@ def test_trajectory_adjoint_fd(orc):
             pm = [eps.copy(), sig.copy()]
             pp[which][p] += hp
             pm[which][p] -= hp
-            lp = traj_loss(orc, x0, v0, L, rc, rl, dt, T, *pp, types, xref)[0]
-            lm = traj_loss(orc, x0, v0, L, rc, rl, dt, T, *pm, types, xref)[0]
+            lp = traj_loss(orc, x0, v0, L, rc, rl, dt, T, *pp, types, xref, mass)[0]
+            lm = traj_loss(orc, x0, v0, L, rc, rl, dt, T, *pm, types, xref, mass)[0]
             assert grad[p] == pytest.approx((lp - lm) / (2 * hp), rel=1e-5)
