@@ -77,27 +77,47 @@ def copy_calibration():
 
 
 EVENT_EVERY = 10
+WINDOWS = 3
 
 
-def md_run(w, s, precision, steps, warmup, dev):
-    """Time `steps` MD steps after `warmup`; returns (seconds, force-call ms list, sim)."""
+def md_run(w, s, precision, steps, warmup, dev, windows=WINDOWS, kind=None):
+    """Time `windows` consecutive windows of `steps` MD steps each after `warmup` steps;
+    returns (median window seconds, all window seconds, force-call ms list, sim).
+
+    Python's garbage collector is run before and held off during the windows: a full
+    collection of this process's objects costs tens of milliseconds, which would land
+    inside a short window as a host-side stall between launches."""
+    import gc
     import torch
     from paper_2109_09056_amd import md, ops
-    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=precision, kind=ops.FULL, dt=w.dt,
+    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=precision,
+                   kind=ops.FULL if kind is None else kind, dt=w.dt,
                    rebuild_every=w.rebuild_every, device=dev)
     sim.load(s["x"], s["v"])
     sim.step(warmup)
-    # events around every EVENT_EVERY-th force launch: each recorded event costs the
-    # stream a few microseconds, so timing every launch would slow the loop itself
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              if k % EVENT_EVERY == EVENT_EVERY // 2 else None for k in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps, force_events=iter(events))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    force_ms = [e[0].elapsed_time(e[1]) for e in events if e is not None]
-    return t1 - t0, force_ms, sim
+    times, force_ms = [], []
+    for _ in range(windows):
+        # events around every EVENT_EVERY-th force launch: each recorded event costs the
+        # stream a few microseconds, so timing every launch would slow the loop itself
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  if k % EVENT_EVERY == EVENT_EVERY // 2 else None for k in range(steps)]
+        for e in events:  # HIP events are created at their first record: do it here
+            if e is not None:
+                e[0].record()
+                e[1].record()
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps, force_events=iter(events))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        finally:
+            gc.enable()
+        times.append(t1 - t0)
+        force_ms += [e[0].elapsed_time(e[1]) for e in events if e is not None]
+    return statistics.median(times), times, force_ms, sim
 
 
 def event_time(fn, reps):
@@ -186,6 +206,28 @@ def bwd_fwd_trajectory(dev):
             "kernel_ratio": round(tb / tf, 3)}
 
 
+def config1_matrix(dev, steps=1000, warmup=50):
+    """The 32,000-atom liquid (fcc 20^3 cells), 1,000 steps rebuilding every 20, in each of
+    FP64 / mixed x full / half lists: atom-steps/s (median of three windows) and the
+    average force launch (full lists: the fused step launch; half lists: the force
+    call, whose integration runs as separate launches)."""
+    import lj_inputs as li
+    from paper_2109_09056_amd import ops
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    out = {}
+    for pname, prec in (("fp64", ops.FP64), ("mixed", ops.MIXED)):
+        for kname, kind in (("full", ops.FULL), ("half", ops.HALF)):
+            t, tw, fms, sim = md_run(w, s, prec, steps, warmup, dev, kind=kind)
+            out[f"{pname}_{kname}"] = {
+                "value": round(w.natoms * steps / t, 1), "ms_per_step": round(t * 1e3 / steps, 5),
+                "force_launch_us": round(statistics.mean(fms) * 1e3, 3),
+                "mean_list_length": round(float(sim.nl.nnbr.double().mean().item()), 3)}
+            del sim
+    out["natoms"], out["steps"], out["unit"] = w.natoms, steps, "atom-steps/s"
+    return out
+
+
 def mixed_error(w, sim):
     """Mixed against FP64 forces and energies at the final positions of the mixed run."""
     import torch
@@ -260,7 +302,7 @@ def shard_share(dev, steps=200, warmup=40):
     sub = {"x": np.ascontiguousarray(xs[keep]), "v": np.ascontiguousarray(s["v"][keep])}
     shard = types.SimpleNamespace(box=edge, rc=w.rc, skin=w.skin, dt=w.dt,
                                   rebuild_every=w.rebuild_every)
-    t, fms, sim = md_run(shard, sub, ops.MIXED, steps, warmup, dev)
+    t, _, fms, sim = md_run(shard, sub, ops.MIXED, steps, warmup, dev)
     n_all, n_own = int(keep.sum()), int(owned.sum())
     return {"owned_atoms": n_own, "ghost_atoms": n_all - n_own, "box_edge": round(float(edge[0]), 4),
             "steps": steps, "ms_per_step": round(t * 1e3 / steps, 5),
@@ -430,25 +472,55 @@ def spme_cpu_oracle(rows=256):
                       f"{rows} sampled atoms, scaled to {w.natoms} atoms ({total:.0f} s)"}
 
 
-def cpu_baseline(w, s, target_s):
-    """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input."""
+def cpu_model():
+    """The host CPU's model name and logical CPU count, from /proc/cpuinfo."""
+    names = []
+    try:
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+    except OSError:
+        pass
+    return (names[0] if names else "unknown"), len(names)
+
+
+def _oracle_rate(w, s, target_s, rng):
+    """Oracle atom-evaluations/s on a sample sized to about target_s of CPU time."""
     import numpy as np
     import oracle
     n = w.natoms
-    rng = np.random.default_rng(0)
-    probe = np.sort(rng.choice(n, 256, replace=False))
+    probe = np.sort(rng.choice(n, 128, replace=False))
     t0 = time.perf_counter()
     oracle.forces(s["x"], w.box, w.rc, sel=probe)
     per_atom = (time.perf_counter() - t0) / probe.size
-    m = int(min(n, max(512, target_s / max(per_atom, 1e-9))))
+    m = int(min(n, max(128, target_s / max(per_atom, 1e-9))))
     rows = np.sort(rng.choice(n, m, replace=False))
     t0 = time.perf_counter()
     oracle.forces(s["x"], w.box, w.rc, sel=rows)
     dt = time.perf_counter() - t0
-    return {"value": round(m / dt, 3), "unit": "atom-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"all-pairs FP64 forces+energy for {m} sampled atoms of the {n}-atom "
-                      f"input (one force evaluation each, {dt:.1f} s)"}
+    return m / dt, m, dt
+
+
+def cpu_baseline(w, s, target_s):
+    """The oracle (plain all-pairs FP64, OpenMP) on sampled atoms of the same input, with
+    all the threads OpenMP gives it and with one thread."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(0)
+    cores = oracle.num_threads()
+    model, logical = cpu_model()
+    v_all, m_all, dt_all = _oracle_rate(w, s, target_s, rng)
+    oracle.set_threads(1)
+    try:
+        v_one, m_one, dt_one = _oracle_rate(w, s, target_s / 2, rng)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": round(v_all, 3), "unit": "atom-steps/s", "cores": cores,
+            "kind": "oracle", "cpu_model": model, "logical_cpus": logical,
+            "one_thread": {"value": round(v_one, 3), "cores": 1,
+                           "sample": f"{m_one} sampled atoms ({dt_one:.1f} s)"},
+            "sample": f"all-pairs FP64 forces+energy for {m_all} sampled atoms of the "
+                      f"{w.natoms}-atom input (one force evaluation each, {dt_all:.1f} s, "
+                      f"{cores} threads); the same on one thread beside it"}
 
 
 def main():
@@ -481,7 +553,7 @@ def main():
     n = w.natoms
     log(f"[bench] workload {w.name}: {n} atoms, box {w.box[0]:.4f}, mixed path, "
         f"{args.warmup} warmup + {args.steps} timed steps")
-    t_mixed, fms, sim = md_run(w, s, ops.MIXED, args.steps, args.warmup, dev)
+    t_mixed, tw_mixed, fms, sim = md_run(w, s, ops.MIXED, args.steps, args.warmup, dev)
     value = n * args.steps / t_mixed
     nbar = float(sim.nl.nnbr.double().mean().item())
     force_ms = statistics.mean(fms)
@@ -496,6 +568,8 @@ def main():
         "metric": "atom-steps/s LJ force+neighbor, mixed vs FP64, 500k atoms; bwd/fwd time ratio",
         "value": round(value, 1), "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3 / args.steps, 5),
+        "timing": {"windows": len(tw_mixed), "statistic": "median window",
+                   "window_ms_per_step": [round(t * 1e3 / args.steps, 5) for t in tw_mixed]},
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed: f64 displacement/cutoff/accumulation, f32 pair math",
         "data": "synthetic (seeded jittered fcc LJ liquid, Maxwell velocities)",
@@ -513,21 +587,25 @@ def main():
                      "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
     }
     if not args.no_extras:
-        t64, f64ms, sim64 = md_run(w, s, ops.FP64, args.steps, args.warmup, dev)
+        t64, tw64, f64ms, sim64 = md_run(w, s, ops.FP64, args.steps, args.warmup, dev)
         line["fp64"] = {"value": round(n * args.steps / t64, 1), "unit": "atom-steps/s",
                         "ms_per_step": round(t64 * 1e3 / args.steps, 5),
+                        "window_ms_per_step": [round(t * 1e3 / args.steps, 5) for t in tw64],
                         "step_launch_us": round(statistics.mean(f64ms) * 1e3, 3),
-                        "mixed_over_fp64": round(t64 / t_mixed, 4)}
+                        "mixed_over_fp64": round(t64 / t_mixed, 4),
+                        "mixed_over_fp64_step_kernel": round(statistics.mean(f64ms) / force_ms, 4)}
         log(f"[bench] fp64: {t64 * 1e3 / args.steps:.4f} ms/step")
         line["fp64"]["mixed_error_vs_fp64"] = mixed_error(w, sim)
         line["traversal_study"] = traversal_study(w, sim)
         log(f"[bench] traversal study: {line['traversal_study']}")
         line["rebuild_us"] = rebuild_time(sim)
+        line["lj32k_matrix"] = config1_matrix(dev)
+        log(f"[bench] 32k matrix: {line['lj32k_matrix']}")
         line["bwd_fwd"] = {"force_matching_32k": bwd_fwd_forcematching(dev),
                            "trajectory_256k": bwd_fwd_trajectory(dev)}
         w2 = li.WORKLOADS["lj2m"]
         s2 = li.make_system(w2)
-        t2, f2ms, sim2 = md_run(w2, s2, ops.MIXED, w2.steps, 40, dev)
+        t2, _, f2ms, sim2 = md_run(w2, s2, ops.MIXED, w2.steps, 40, dev)
         nb2 = float(sim2.nl.nnbr.double().mean().item())
         line["scale_2m"] = {"natoms": w2.natoms, "steps": w2.steps,
                             "value": round(w2.natoms * w2.steps / t2, 1), "unit": "atom-steps/s",

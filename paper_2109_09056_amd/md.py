@@ -137,6 +137,11 @@ class LJSim:
         for op in (ops.OP_FORCES, ops.OP_INTEGRATE, ops.OP_MD_CHAIN):
             self._ws[op] = torch.empty(max(ops.workspace_bytes(op, n), 8), dtype=torch.uint8,
                                        device=dev)
+        # the re-sort's counters and scan rows, allocated once so a rebuild allocates nothing
+        nc = ops.grid(self.L, self.rlist)
+        self._ws[ops.OP_BIN] = torch.empty(
+            max(ops.workspace_bytes(ops.OP_BIN, n, ncells=nc[0] * nc[1] * nc[2]), 8),
+            dtype=torch.uint8, device=dev)
         self.rebuild()
         self.compute_forces(energy=True)
         ops.integrate(KINETIC, self.dt, self.mass, self.L, None, self.v, None, ke=self.ke,
