@@ -57,6 +57,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Sets the thread count of later parallel regions (no effect without OpenMP). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static int packed_index(int a, int b, int T) {
   if (a > b) { int t = a; a = b; b = t; }
   return a * T - a * (a - 1) / 2 + (b - a);
@@ -175,6 +184,29 @@ void orc_neighbor_fill(int64_t n, const double *x, const double L[3], double rli
   }
 }
 
+/* The same relation as unordered pairs, each once: for every atom i the j > i
+ * with r^2 < rlist^2, in ascending j, one pass over j > i (half the pair tests
+ * of the two passes above).  Row i goes to upper[i*cap ..]; len[i] is its true
+ * length, which may exceed cap (then the row is cut and the caller retries with
+ * a larger cap). */
+void orc_neighbor_upper(int64_t n, const double *x, const double L[3], double rlist, int32_t cap,
+                        int32_t *upper, int32_t *len) {
+  double rl2 = rlist * rlist;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t c = 0;
+    int32_t *row = upper + (int64_t)cap * i;
+    for (int64_t j = i + 1; j < n; ++j) {
+      double d[3];
+      if (displacement(x + 3 * i, x + 3 * j, L, d) < rl2) {
+        if (c < cap) row[c] = (int32_t)j;
+        ++c;
+      }
+    }
+    len[i] = c;
+  }
+}
+
 /* -------------------------------------------------------------- forces --- */
 
 /* One row of the force sum.  js == NULL: all j != i; else the listed j. */
@@ -243,23 +275,32 @@ void orc_forces(int64_t n, const double *x, const int32_t *type, int T, const do
 
 /* Forces over a given CSR full list (offsets[n+1], nbr): the Verlet-list
  * mirror of the same definitions, used to follow a trajectory whose list is
- * rebuilt only every few steps. */
+ * rebuilt only every few steps.  npairs (may be NULL): unordered pairs of the
+ * list within rc, per packed type pair. */
 void orc_forces_list(int64_t n, const double *x, const int32_t *type, int T,
                      const double *eps, const double *sig, const double L[3], double rc,
                      const int64_t *offsets, const int32_t *nbr, double *F, double *e,
-                     double *W) {
+                     double *W, int64_t *npairs) {
+  int P = T * (T + 1) / 2;
   double *Wrow = (double *)calloc((size_t)n * 6, sizeof(double));
+  int64_t *prow = npairs ? (int64_t *)calloc((size_t)n * P, sizeof(int64_t)) : NULL;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
     force_row(i, n, x, type, T, eps, sig, L, rc, nbr + offsets[i], offsets[i + 1] - offsets[i],
-              F + 3 * i, e + i, Wrow + 6 * i, NULL);
+              F + 3 * i, e + i, Wrow + 6 * i, prow ? prow + (int64_t)P * i : NULL);
   }
   if (W) {
     for (int q = 0; q < 6; ++q) W[q] = 0.0;
     for (int64_t i = 0; i < n; ++i)
       for (int q = 0; q < 6; ++q) W[q] += Wrow[6 * i + q];
   }
+  if (npairs) {
+    for (int p = 0; p < P; ++p) npairs[p] = 0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int p = 0; p < P; ++p) npairs[p] += prow[(int64_t)P * i + p];
+  }
   free(Wrow);
+  free(prow);
 }
 
 /* ------------------------------------------------------------- adjoint --- */

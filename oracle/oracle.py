@@ -44,15 +44,17 @@ def lib():
             L.orc_neighbor_count.argtypes = [_i64, _D, _D, _dbl, _i64, _VP, _I32]
             L.orc_neighbor_count.restype = _i64
             L.orc_neighbor_fill.argtypes = [_i64, _D, _D, _dbl, _i64, _VP, _I64, _I32]
+            L.orc_neighbor_upper.argtypes = [_i64, _D, _D, _dbl, ctypes.c_int32, _I32, _I32]
             L.orc_forces.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl, _i64,
                                      _VP, _D, _D, _D, _VP]
             L.orc_forces_list.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl,
-                                          _I64, _I32, _D, _D, _D]
+                                          _I64, _I32, _D, _D, _D, _VP]
             L.orc_force_vjp.argtypes = [_i64, _D, _VP, ctypes.c_int, _D, _D, _D, _dbl, _VP,
                                         _VP, _D, _D, _D, _D]
             L.orc_kick_drift.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _VP]
             L.orc_kick.argtypes = [_i64, _D, _D, _dbl, _dbl]
             L.orc_num_threads.restype = ctypes.c_int
+            L.orc_set_threads.argtypes = [ctypes.c_int]
             L.orc_sph_kernel.argtypes = [_i64, _D, _dbl, _VP, _VP]
             L.orc_sph_density.argtypes = [_i64, _D, _D, _dbl, _dbl, _i64, _VP, _D]
             L.orc_sph_accel.argtypes = [_i64, _D, _D, _dbl, _dbl, _dbl, _dbl, _D, _i64, _VP, _D]
@@ -85,6 +87,11 @@ def ntypes_of(eps) -> int:
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ binning --
@@ -124,9 +131,13 @@ def neighbor_lists(x, L, rlist, sel=None):
     """Full Verlet list by brute force: CSR (offsets, nbr), each row j-ascending.
 
     Rows are all atoms, or the atoms in sel (then offsets has len(sel)+1 entries).
+    All rows are formed from the unordered pairs (one brute-force pass over j > i);
+    selected rows by a count pass and a fill pass over all j.
     """
     x = _f64(x)
     n = x.shape[0]
+    if sel is None and n > 0:
+        return full_from_upper(upper_pairs(x, L, rlist), n)
     sel_a = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
     rows = n if sel_a is None else sel_a.size
     counts = np.zeros(rows, dtype=np.int32)
@@ -136,6 +147,36 @@ def neighbor_lists(x, L, rlist, sel=None):
     nbr = np.zeros(max(int(offsets[-1]), 1), dtype=np.int32)
     lib().orc_neighbor_fill(n, x, _box(L), float(rlist), rows, _ptr(sel_a), offsets, nbr)
     return offsets, nbr[:offsets[-1]]
+
+
+def upper_pairs(x, L, rlist, cap=96):
+    """Every unordered pair within rlist once, by brute force over j > i: a [P, 2]
+    int64 array of (i, j), i < j, sorted by i then j."""
+    x = _f64(x)
+    n = x.shape[0]
+    while True:
+        upper = np.zeros(max(n * cap, 1), dtype=np.int32)
+        ln = np.zeros(max(n, 1), dtype=np.int32)
+        lib().orc_neighbor_upper(n, x, _box(L), float(rlist), cap, upper, ln)
+        top = int(ln[:n].max()) if n else 0
+        if top <= cap:
+            break
+        cap = top
+    ln = ln[:n]
+    keep = np.arange(cap)[None, :] < ln[:, None]
+    j = upper[:n * cap].reshape(n, cap)[keep].astype(np.int64)
+    i = np.repeat(np.arange(n, dtype=np.int64), ln)
+    return np.stack([i, j], axis=1)
+
+
+def full_from_upper(pairs, n):
+    """CSR full list (offsets, nbr), rows j-ascending, from the unordered pairs."""
+    i = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    j = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    order = np.argsort(i * n + j, kind="stable")
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(i, minlength=n), out=offsets[1:])
+    return offsets, j[order].astype(np.int32)
 
 
 def half_pairs(offsets, nbr, rows=None) -> np.ndarray:
@@ -171,7 +212,10 @@ def forces(x, L, rc, eps=(1.0,), sigma=(1.0,), types=None, sel=None):
     return F, e, W, npairs
 
 
-def forces_list(x, L, rc, offsets, nbr, eps=(1.0,), sigma=(1.0,), types=None):
+def forces_list(x, L, rc, offsets, nbr, eps=(1.0,), sigma=(1.0,), types=None,
+                with_pairs=False):
+    """F, e, W over a given CSR full list; with_pairs adds the list's unordered pairs
+    within rc per packed type pair."""
     x = _f64(x)
     n = x.shape[0]
     eps = _f64(np.atleast_1d(eps))
@@ -180,10 +224,11 @@ def forces_list(x, L, rc, offsets, nbr, eps=(1.0,), sigma=(1.0,), types=None):
     F = np.zeros((n, 3))
     e = np.zeros(n)
     W = np.zeros(6)
+    npairs = np.zeros(eps.size, dtype=np.int64) if with_pairs else None
     lib().orc_forces_list(n, x, _ptr(t), ntypes_of(eps), eps, sigma, _box(L), float(rc),
                           np.ascontiguousarray(offsets, dtype=np.int64),
-                          np.ascontiguousarray(nbr, dtype=np.int32), F, e, W)
-    return F, e, W
+                          np.ascontiguousarray(nbr, dtype=np.int32), F, e, W, _ptr(npairs))
+    return (F, e, W, npairs) if with_pairs else (F, e, W)
 
 
 def force_vjp(x, L, rc, g, eps=(1.0,), sigma=(1.0,), types=None, offsets=None, nbr=None):
@@ -266,20 +311,33 @@ def run_nve(x, v, L, rc, rlist, dt, steps, rebuild_every=20, eps=(1.0,), sigma=(
 
 # ------------------------------------------------------- trajectory adjoint --
 
-def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None, mass=1.0):
-    """Forward velocity Verlet with one list built at step 0 (steps <= rebuild cadence).
+def trajectory(x0, v0, L, rc, rlist, dt, steps, eps, sigma, types=None, mass=1.0, lst=None,
+               pairs=None):
+    """Forward velocity Verlet with one list built at step 0 (steps <= rebuild cadence),
+    or the given list lst.
 
     Returns (xs, v_T, unwrapped x_T, lst): xs[k] is the wrapped position at step k.
+    pairs: optional list that receives, for steps 0..steps, the number of unordered
+    pairs of the list within rc (all type pairs).
     """
     x = _f64(x0).copy()
     v = _f64(v0).copy()
     img = np.zeros(x.shape, dtype=np.int32)
-    lst = neighbor_lists(x, L, rlist)
-    F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+    if lst is None:
+        lst = neighbor_lists(x, L, rlist)
+
+    def force():
+        out = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types,
+                          with_pairs=pairs is not None)
+        if pairs is not None:
+            pairs.append(int(out[3].sum()))
+        return out[0]
+
+    F = force()
     xs = [x.copy()]
     for _ in range(steps):
         kick_drift(x, v, F, dt, L, mass=mass, img=img)
-        F, _, _ = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+        F = force()
         kick(v, F, dt, mass=mass)
         xs.append(x.copy())
     return xs, v, x + img * _box(L), lst

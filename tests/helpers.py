@@ -34,6 +34,18 @@ def decode_rows(nbr, nnbr, maxn):
     return [full[i, :nnbr[i]] for i in range(n)]
 
 
+def list_pairs(nbr, nnbr, maxn):
+    """(i, j) arrays of every entry of a tiled-ELL list, in sorted-order indices, row-major
+    (vectorised decode for large lists)."""
+    nbr = np.asarray(nbr)
+    nnbr = np.asarray(nnbr).astype(np.int64)
+    n = nnbr.size
+    tiles = max((n + 63) // 64, 1)
+    full = nbr[:tiles * maxn * 64].reshape(tiles, maxn, 64).transpose(0, 2, 1).reshape(-1, maxn)
+    keep = np.arange(maxn)[None, :] < nnbr[:, None]
+    return np.repeat(np.arange(n, dtype=np.int64), nnbr), full[:n][keep].astype(np.int64)
+
+
 def pair_array(rows_i, rows_j):
     """Sorted unique [P, 2] int64 array of (i, j) pairs."""
     a = np.stack([np.asarray(rows_i, dtype=np.int64), np.asarray(rows_j, dtype=np.int64)], 1)

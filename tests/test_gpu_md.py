@@ -222,11 +222,12 @@ def test_md_bitwise_repeatable(dev):
 
 @pytest.fixture(scope="module")
 def oracle_32k_run(orc):
-    """The oracle's own Verlet-list trajectory of the 32,000-atom liquid, 100 steps."""
+    """The oracle's own Verlet-list trajectory of the 32,000-atom liquid, 1,000 steps (the
+    lattice start melts; by step 1,000 it is an equilibrated liquid at T ~ 0.7)."""
     w = li.WORKLOADS["lj32k"]
     s = li.make_system(w)
-    _, _, _, thermo, snaps, _ = orc.run_nve(s["x"], s["v"], w.box, w.rc, w.rlist, w.dt, 100,
-                                            mode="verlet", record={20, 100})
+    _, _, _, thermo, snaps, _ = orc.run_nve(s["x"], s["v"], w.box, w.rc, w.rlist, w.dt, 1000,
+                                            mode="verlet", record={20, 100, 1000})
     return w, s, thermo, snaps
 
 
@@ -285,20 +286,39 @@ def test_graph_replay_matches_eager(dev, prec):
         assert torch.equal(ea, eb)
 
 
+@pytest.mark.parametrize("snap", [100, 1000])
+@pytest.mark.parametrize("kind", ["full", "half"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_forces_at_oracle_snapshot(dev, orc, oracle_32k_run, prec):
-    """Every atom's force and energy, and E and W, at the oracle's own step-100 positions of
-    the 32,000-atom run (the lattice melting into a liquid), against the oracle there."""
+def test_forces_at_oracle_snapshot(dev, orc, oracle_32k_run, snap, kind, prec):
+    """Every atom's force and energy, and E and W, at the oracle's own positions of the
+    32,000-atom run, against the oracle there: step 100 (the lattice melting) and step
+    1,000 (the equilibrated liquid, where per-atom energies are smallest), on full and
+    half lists; the lists themselves against the oracle's brute-force sets."""
     import torch
+    from helpers import list_pairs
     from paper_2109_09056_amd import md, ops
     w, s, thermo, snaps = oracle_32k_run
-    x = snaps[100][0]
+    x = snaps[snap][0]
+    n = w.natoms
     Fo, eo, Wo, _ = orc.forces(x, w.box, w.rc)
     Eo = eo.sum()
     P = ops.FP64 if prec == "fp64" else ops.MIXED
-    sim = md.LJSim(w.box, precision=P, device=dev)
+    K = ops.FULL if kind == "full" else ops.HALF
+    sim = md.LJSim(w.box, precision=P, kind=K, device=dev)
     sim.load(x, None)
-    F, e, ev = ops.compute_forces(w.box, P, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x,
+    up = orc.upper_pairs(x, w.box, w.rlist)
+    i, j = list_pairs(sim.nl.nbr.cpu().numpy(), sim.nl.nnbr.cpu().numpy(), sim.nl.maxn)
+    ids = sim.ids.cpu().numpy()
+    a, b = ids[i], ids[j]
+    want = up[:, 0] * n + up[:, 1]
+    if K == ops.FULL:  # both directions of every pair, nothing else
+        lo = a < b
+        assert a.size == 2 * want.size
+        assert np.array_equal(np.sort(a[lo] * n + b[lo]), want)
+        assert np.array_equal(np.sort(b[~lo] * n + a[~lo]), want)
+    else:
+        assert np.array_equal(np.sort(np.minimum(a, b) * n + np.maximum(a, b)), want)
+    F, e, ev = ops.compute_forces(w.box, P, K, w.rc, sim.eps, sim.sigma, sim.x,
                                   sim.types, sim.nl.nbr, sim.nl.nnbr, sim.nl.maxn)
     Fg = sim.in_caller_order(F).cpu().numpy()
     eg = sim.in_caller_order(e.reshape(-1, 1)).cpu().numpy().reshape(-1)

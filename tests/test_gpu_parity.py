@@ -376,6 +376,36 @@ def test_500k_sampled_neighbors_and_forces(dev, orc, big):
             assert (np.abs(es - eo) / np.abs(eo)).max() <= MIXED_E_TOL
 
 
+@pytest.mark.timeout(900)
+def test_500k_every_row_full_and_half(dev, orc):
+    """Every row of the 500k start's full and half lists, by original id, against the
+    oracle's brute-force relation over all pairs (1.25e11 pair tests): the full list holds
+    each unordered pair in both directions and nothing else, the half list each once."""
+    from helpers import list_pairs
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj500k"]
+    x = li.positions(w)
+    n = w.natoms
+    up = orc.upper_pairs(x, w.box, w.rlist)
+    key = up[:, 0] * n + up[:, 1]  # ascending: rows by i, then j
+    del up
+    xs, _, _, ids, cs = ops.bin(w.box, w.rlist, T(x, dev, None))
+    ids = ids.cpu().numpy()
+    for kind in (ops.FULL, ops.HALF):
+        nl = md.NeighborList(w.box, w.rlist, kind, device=dev).build(xs, cs)
+        i, j = list_pairs(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn)
+        a, b = ids[i], ids[j]
+        del i, j, nl
+        if kind == ops.FULL:
+            assert a.size == 2 * key.size
+            lo = a < b
+            assert np.array_equal(np.sort(a[lo] * n + b[lo]), key)
+            assert np.array_equal(np.sort(b[~lo] * n + a[~lo]), key)
+        else:
+            assert a.size == key.size
+            assert np.array_equal(np.sort(np.minimum(a, b) * n + np.maximum(a, b)), key)
+
+
 def test_500k_steps_properties(dev, big):
     """40 steps (two rebuilds) at 500k: momentum stays zero, mixed and FP64 runs from the
     same start stay together, and the full list stays symmetric."""

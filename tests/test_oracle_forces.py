@@ -115,3 +115,21 @@ def test_selected_rows_and_list_mode_agree(orc):
     Fl, el, Wl = orc.forces_list(x, w.box, w.rc, off, nb)
     np.testing.assert_allclose(Fl, F, rtol=0, atol=1e-12)
     np.testing.assert_allclose(Wl, W, rtol=1e-13)
+
+
+def test_pair_counts_within_cutoff(orc):
+    """Unordered pairs within rc per packed type pair, over all pairs and over a list,
+    against a NumPy count by type that shares no code with the oracle."""
+    from helpers import pairs_within
+    w, x = jittered(index=17, jitter=0.2)
+    types = (np.arange(x.shape[0]) % 2).astype(np.int32)
+    eps, sig = [1.0, 0.9, 1.1], [1.0, 1.05, 0.95]
+    _, _, _, npairs = orc.forces(x, w.box, w.rc, eps, sig, types)
+    off, nb = orc.neighbor_lists(x, w.box, w.rlist)
+    _, _, _, np_list = orc.forces_list(x, w.box, w.rc, off, nb, eps, sig, types,
+                                       with_pairs=True)
+    a, b = x[types == 0], x[types == 1]
+    n00, n11 = pairs_within(a, w.box, w.rc), pairs_within(b, w.box, w.rc)
+    n01 = pairs_within(x, w.box, w.rc) - n00 - n11
+    assert list(npairs) == [n00, n01, n11] and list(np_list) == [n00, n01, n11]
+    assert n01 > 0 and n00 > 0

@@ -54,6 +54,27 @@ def test_selected_rows_match_full(orc):
         assert np.array_equal(sn[so[k]:so[k + 1]], nb[off[i]:off[i + 1]])
 
 
+@pytest.mark.parametrize("case", ["liquid4000", "clump"])
+def test_pair_pass_matches_row_passes(orc, case):
+    """Whole lists (one pass over the unordered pairs, rows cut at a capacity and
+    re-run when cut) equal the row-by-row count and fill passes over all j."""
+    if case == "liquid4000":
+        w = li.Workload("liquid4000", 9, cells=10)
+        x, L = li.positions(w), w.box
+    else:  # 300 atoms inside one rlist-sized ball: rows far beyond the first capacity
+        L = np.array([20.0, 21.0, 22.0])
+        x = li.random_gas(300, np.array([1.6, 1.6, 1.6]), seed=4) + 18.9
+        x = np.where(x >= L, x - L, x)
+    n = x.shape[0]
+    off, nb = orc.neighbor_lists(x, L, 2.8)
+    so, sn = orc.neighbor_lists(x, L, 2.8, sel=np.arange(n))
+    assert np.array_equal(off, so) and np.array_equal(nb, sn)
+    up = orc.upper_pairs(x, L, 2.8)
+    assert np.array_equal(up, orc.half_pairs(so, sn))
+    if case == "clump":
+        assert np.diff(off).max() > 96
+
+
 def test_half_pairs(orc):
     w = li.WORKLOADS["lj256"]
     x = li.positions(w)
