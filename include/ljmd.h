@@ -37,7 +37,8 @@
  *  - Positions, velocities, forces: FP64, [n][3] row-major (x, y, z per atom).
  *  - Every array argument is a DEVICE pointer owned by the caller, except
  *    where marked (host).  The library allocates and frees nothing and keeps
- *    no state between calls.  Outputs never alias inputs unless stated.
+ *    no state between calls, except the static scratch array of
+ *    ljmd_md_step_noalloc.  Outputs never alias inputs unless stated.
  *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).  All
  *    device work is enqueued asynchronously on it; no call synchronizes.
  *  - Return value: LJMD_OK or an error code; no exception crosses the ABI.
@@ -264,6 +265,32 @@ int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
                  const double *x, const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
                  int32_t maxn, double dt, double mass, double *v, double *x_next, int open_next,
                  double *F, double *e_atom, double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_md_step_noalloc -- ljmd_md_step without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  It runs the same
+ * kernels with the same results, bitwise; its per-block energy/virial/kinetic
+ * rows go to a static device array of LJMD_NOALLOC_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends.  The first call on a
+ * device looks up that device's copy (hipGetSymbolAddress, the device current
+ * at the call; `stream` must belong to it); no call allocates or frees memory.
+ * Limits and sharing:
+ *   n        at most LJMD_NOALLOC_MAX_ATOMS (else LJMD_EWORKSPACE, nothing runs)
+ *   calls that overlap on one GPU (different streams or threads, or another
+ *   call enqueued before this one's launch has run) share the array and race:
+ *   serialize them on one stream.  Each call writes every row it reads, so the
+ *   previous call's contents never enter a result.
+ * Other arguments and errors as in ljmd_md_step.
+ */
+#define LJMD_NOALLOC_SCRATCH_BYTES (2u << 20)
+#define LJMD_NOALLOC_MAX_ATOMS 4194304 /* (2 MiB / 64 B per 128-atom block) * 128 */
+int ljmd_md_step_noalloc(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                         const double *eps_packed, const double *sigma_packed, int64_t n,
+                         const double *x, const int32_t *type, const int32_t *nbr,
+                         const int32_t *nnbr, int32_t maxn, double dt, double mass, double *v,
+                         double *x_next, int open_next, double *F, double *e_atom, double *ev,
+                         void *stream);
 
 /*
  * ljmd_md_step_chained -- ljmd_md_step without its own column-sum launch: the

@@ -23,6 +23,8 @@ SPME_MAX_GRID = 256
 MAX_TYPES = 8
 TILE = 64
 MAX_TEAM = 16
+NOALLOC_SCRATCH_BYTES = 2 << 20  # static scratch of ljmd_md_step_noalloc
+NOALLOC_MAX_ATOMS = 4194304
 
 
 class Box(ctypes.Structure):
@@ -52,6 +54,8 @@ SIGNATURES = {
                                    _p, _p, _p, _p, _int, _p, _sz, _p]),
     "ljmd_md_step": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32, _dbl,
                             _dbl, _p, _p, _int, _p, _p, _p, _p, _sz, _p]),
+    "ljmd_md_step_noalloc": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p,
+                                    _i32, _dbl, _dbl, _p, _p, _int, _p, _p, _p, _p]),
     "ljmd_md_step_chained": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p, _i32,
                                     _dbl, _dbl, _p, _p, _int, _p, _p, _int, _p, _p, _sz, _p]),
     "ljmd_md_step_sums": (_int, [_i64, _int, _p, _sz, _p, _p]),

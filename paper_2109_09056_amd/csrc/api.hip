@@ -4,6 +4,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace ljmd {
@@ -17,6 +19,7 @@ int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t 
                  const int32_t *cell_start, int32_t maxn, int32_t *nbr, int32_t *nnbr,
                  int32_t *max_count, hipStream_t st);
 size_t force_workspace(int64_t n);
+int64_t force_workspace_atoms();
 int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t ntypes,
                   const double *eps, const double *sig, int64_t n, const double *x,
                   const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,
@@ -182,6 +185,39 @@ static int check_md_step(const ljmd_box *box, int precision, double rc, int32_t 
     return set_error(LJMD_EINVAL, "x/nbr/nnbr/v/x_next is NULL");
   if (n > 0 && open_next && x_next == x)
     return set_error(LJMD_EINVAL, "x_next must not alias x");
+  return LJMD_OK;
+}
+
+// Scratch of the allocation-free step (ljmd_md_step_noalloc): the per-block energy /
+// virial / kinetic rows of one fused step launch.  Every GPU the library runs on holds
+// its own copy until the process ends.  In host code the array's name is a host-side
+// stand-in, not a device address: kernels get the per-device address that
+// hipGetSymbolAddress returns.
+constexpr size_t kScratchBytes = LJMD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up once per device.
+static int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(LJMD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(LJMD_EHIP, "device %d beyond the %d the scratch table holds", dev,
+                     kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(LJMD_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return LJMD_OK;
 }
 
@@ -451,6 +487,28 @@ int ljmd_md_step(const ljmd_box *box, int precision, double rc, int32_t ntypes,
   return launch_md_step(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x, type,
                         nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, ev,
                         (double *)ws, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int ljmd_md_step_noalloc(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                         const double *eps_packed, const double *sigma_packed, int64_t n,
+                         const double *x, const int32_t *type, const int32_t *nbr,
+                         const int32_t *nnbr, int32_t maxn, double dt, double mass, double *v,
+                         double *x_next, int open_next, double *F, double *e_atom, double *ev,
+                         void *stream) {
+  LJMD_TRY(check_md_step(box, precision, rc, ntypes, eps_packed, sigma_packed, n, x, type, nbr,
+                         nnbr, maxn, dt, mass, v, x_next, open_next));
+  if (!ev) return set_error(LJMD_EINVAL, "ev is NULL");
+  if (force_workspace(n) > kScratchBytes)
+    return set_error(LJMD_EWORKSPACE,
+                     "n = %lld needs %zu bytes of step scratch; the static scratch holds %zu "
+                     "(at most %lld atoms): use ljmd_md_step with a workspace",
+                     (long long)n, force_workspace(n), kScratchBytes,
+                     (long long)(kScratchBytes / force_workspace(1)) * force_workspace_atoms());
+  void *rows = nullptr;
+  LJMD_TRY(scratch_address(&rows));
+  return launch_md_step(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n, x, type,
+                        nbr, nnbr, maxn, dt, mass, v, x_next, open_next, F, e_atom, ev,
+                        (double *)rows, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int ljmd_md_step_chained(const ljmd_box *box, int precision, double rc, int32_t ntypes,

@@ -653,6 +653,9 @@ unsigned force_blocks(int64_t n) {
 
 size_t force_workspace(int64_t n) { return (size_t)force_blocks(n) * kEvStride * sizeof(double); }
 
+// Atoms whose partial rows share one row of the force workspace (one block's).
+int64_t force_workspace_atoms() { return kForceThreads; }
+
 int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t ntypes,
                   const double *eps, const double *sig, int64_t n, const double *x,
                   const int32_t *type, const int32_t *nbr, const int32_t *nnbr, int32_t maxn,

@@ -223,3 +223,19 @@ def test_ops_reject_cpu_tensors():
     with pytest.raises(ValueError, match="GPU"):
         ops.bin((10.0, 10.0, 10.0), 2.8, x)
     _ = np  # numpy used by other tests in this module family
+
+
+def test_noalloc_step_limit_on_host(lib):
+    """The allocation-free step's static scratch holds the rows of exactly
+    NOALLOC_MAX_ATOMS atoms; one more is rejected on the host, before any device work."""
+    W = lib.load().ljmd_workspace_bytes
+    m = lib.NOALLOC_MAX_ATOMS
+    assert W(lib.OP_FORCES, m, 0, 1) <= lib.NOALLOC_SCRATCH_BYTES
+    assert W(lib.OP_FORCES, m + 1, 0, 1) > lib.NOALLOC_SCRATCH_BYTES
+    b = lib.make_box((200.0, 200.0, 200.0))
+    fake = ctypes.c_void_p(4096)  # never dereferenced: the call fails its size check first
+    rc = call(lib, "ljmd_md_step_noalloc", ctypes.byref(b), lib.FP64, 2.5, 1, fake, fake, m + 1,
+              fake, fake, fake, fake, 96, 0.005, 1.0, fake, ctypes.c_void_p(8192), 1, fake, fake,
+              fake, None)
+    assert rc == lib.EWORKSPACE
+    assert b"ljmd_md_step with a workspace" in lib.load().ljmd_last_error()
