@@ -586,6 +586,12 @@ def main():
                      "valu_busy": FORCE_VALU_BUSY, "texture_addr_busy": FORCE_TA_BUSY,
                      "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
     }
+    checked, dangerous, dmax = sim.displacement_report()
+    line["stale_list_check"] = {
+        "rebuilds_checked": checked, "dangerous_rebuilds": dangerous,
+        "max_displacement": round(dmax, 4), "skin_half": 0.5 * w.skin,
+        "note": "a window is dangerous when some atom moved more than skin/2 since the list "
+                "was built (pairs inside rc may then be missing from it)"}
     if not args.no_extras:
         t64, tw64, f64ms, sim64 = md_run(w, s, ops.FP64, args.steps, args.warmup, dev)
         line["fp64"] = {"value": round(n * args.steps / t64, 1), "unit": "atom-steps/s",

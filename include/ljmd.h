@@ -94,6 +94,7 @@ extern "C" {
 #define LJMD_OP_EWALD_REAL 8 /* ljmd_ewald_real */
 #define LJMD_OP_SPME 9       /* ljmd_spme_recip; ncells = K[0]*K[1]*K[2] grid points */
 #define LJMD_OP_MD_CHAIN 10  /* ljmd_md_step_chained, ljmd_md_step_sums (two halves) */
+#define LJMD_OP_DISPLACEMENT 11 /* ljmd_max_displacement */
 #define LJMD_SPME_MAX_GRID 256 /* largest grid edge of ljmd_spme_recip */
 
 #define LJMD_MAX_TYPES 8
@@ -462,6 +463,23 @@ int ljmd_spme_recip(const ljmd_box *box, double alpha, int32_t order, const int3
  * ljmd_adjoint_kick: vbar += dt * xbar; g = w * dt * vbar.  [n][3] each. */
 int ljmd_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
                       double *g, void *stream);
+
+/*
+ * ljmd_max_displacement -- the largest squared minimum-image displacement
+ * max_i |x_i - x_ref_i|^2 since the positions x_ref at which a list was built
+ * (same atom order), the test of a dangerous build: a Verlet list of cutoff
+ * rc + skin holds every pair inside rc only while no atom has moved more than
+ * skin/2 since it was built (paper, Introduction: lists are reused between
+ * rebuilds; Cabana "Neighbor List Creation").  With a fixed rebuild cadence a
+ * caller checks it at each rebuild to learn whether the window that ends there
+ * may have missed pairs.
+ *   x, x_ref  [n][3] positions now and at the build; must not alias
+ *   max_d2    device scalar output (0 for n = 0)
+ *   ws        >= ljmd_workspace_bytes(LJMD_OP_DISPLACEMENT, n, 0, 1)
+ * Errors: LJMD_EINVAL (null, aliasing), LJMD_EBOX, LJMD_EWORKSPACE, LJMD_EHIP.
+ */
+int ljmd_max_displacement(const ljmd_box *box, int64_t n, const double *x, const double *x_ref,
+                          double *max_d2, void *ws, size_t ws_bytes, void *stream);
 
 /* Trajectory loss on final positions: d = minimum image of (x - xref) (equal
  * to the unwrapped difference while the two trajectories stay within L/2),

@@ -269,14 +269,16 @@ def kick(v, F, dt, mass=1.0):
 
 
 def run_nve(x, v, L, rc, rlist, dt, steps, rebuild_every=20, eps=(1.0,), sigma=(1.0,),
-            types=None, mode="verlet", record=None):
+            types=None, mode="verlet", record=None, missed=None):
     """Velocity-Verlet NVE run.
 
     mode "verlet": the oracle's own brute-force list, rebuilt every
     rebuild_every steps from step 0 with no displacement check; "allpairs":
     every force call over all pairs.  Returns (x, v, F, thermo) where thermo is
     a list of (step, PE, KE) and `record` (a set of steps) selects snapshots
-    returned in thermo-side dict `snaps`.
+    returned in thermo-side dict `snaps`.  missed (verlet mode): optional list
+    that receives, for every force call, the number of pairs inside rc that the
+    current list does not hold (all pairs inside rc minus the list's).
     """
     x = _f64(x).copy()
     v = _f64(v).copy()
@@ -291,7 +293,12 @@ def run_nve(x, v, L, rc, rlist, dt, steps, rebuild_every=20, eps=(1.0,), sigma=(
             return F, e
         if step % rebuild_every == 0 or lst is None:
             lst = neighbor_lists(x, L, rlist)
-        F, e, W = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+        if missed is None:
+            F, e, W = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types)
+        else:
+            F, e, W, held = forces_list(x, L, rc, lst[0], lst[1], eps, sigma, types,
+                                        with_pairs=True)
+            missed.append(int(forces(x, L, rc, eps, sigma, types)[3].sum() - held.sum()))
         return F, e
 
     F, e = force(0)

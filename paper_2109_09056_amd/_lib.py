@@ -18,7 +18,7 @@ FP64, MIXED = 0, 1
 FULL, HALF = 0, 1
 KICK_DRIFT, KICK, KINETIC, KICK_KICK_DRIFT = 0, 1, 2, 3
 (OP_BIN, OP_FORCES, OP_BACKWARD, OP_INTEGRATE, OP_LOSS, OP_CSR, OP_FORCES_CSR, OP_SPH,
- OP_EWALD_REAL, OP_SPME, OP_MD_CHAIN) = range(11)
+ OP_EWALD_REAL, OP_SPME, OP_MD_CHAIN, OP_DISPLACEMENT) = range(12)
 SPME_MAX_GRID = 256
 MAX_TYPES = 8
 TILE = 64
@@ -73,6 +73,7 @@ SIGNATURES = {
     "ljmd_spme_recip": (_int, [_box, _dbl, _i32, ctypes.POINTER(_i32), _i64, _p, _p, _p, _p,
                                _int, _p, _sz, _p]),
     "ljmd_adjoint_kick": (_int, [_i64, _dbl, _dbl, _p, _p, _p, _p]),
+    "ljmd_max_displacement": (_int, [_box, _i64, _p, _p, _p, _p, _sz, _p]),
     "ljmd_traj_loss": (_int, [_box, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "ljmd_scatter_rows": (_int, [_i64, _i32, _p, _p, _p, _p]),
     "ljmd_gather_rows": (_int, [_i64, _i32, _p, _p, _p, _p]),

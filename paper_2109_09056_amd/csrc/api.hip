@@ -65,6 +65,8 @@ int launch_integrate(int stage, double dt, double mass, const BoxK &b, int64_t n
                      double *v, const double *F, double *ke, void *ws, hipStream_t st);
 int launch_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double *vbar,
                         double *g, hipStream_t st);
+int launch_max_displacement(const BoxK &b, int64_t n, const double *x, const double *xref,
+                            double *max_d2, void *ws, hipStream_t st);
 int launch_loss(const BoxK &b, int64_t n, const double *x, const double *xref, double *xbar,
                 double *loss, void *ws, hipStream_t st);
 int launch_scatter_rows(int64_t n, int32_t width, const int64_t *id, const double *src,
@@ -255,7 +257,8 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
     case LJMD_OP_BACKWARD:
       return bwd_workspace(n, ntypes < 1 ? 1 : (ntypes > LJMD_MAX_TYPES ? LJMD_MAX_TYPES : ntypes));
     case LJMD_OP_INTEGRATE:
-    case LJMD_OP_LOSS: return stream_workspace(n);
+    case LJMD_OP_LOSS:
+    case LJMD_OP_DISPLACEMENT: return stream_workspace(n);
     case LJMD_OP_CSR: return csr_workspace(n);
     case LJMD_OP_FORCES_CSR: return csr_force_workspace(n);
     case LJMD_OP_SPH: return sph_workspace(n);
@@ -568,6 +571,17 @@ int ljmd_adjoint_kick(int64_t n, double dt, double w, const double *xbar, double
   if (!isfinite(dt) || !isfinite(w)) return set_error(LJMD_EINVAL, "dt/w not finite");
   if (n > 0 && (!xbar || !vbar || !g)) return set_error(LJMD_EINVAL, "xbar/vbar/g is NULL");
   return launch_adjoint_kick(n, dt, w, xbar, vbar, g, (hipStream_t)stream);
+}
+
+int ljmd_max_displacement(const ljmd_box *box, int64_t n, const double *x, const double *x_ref,
+                          double *max_d2, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_n(n));
+  if (!max_d2) return set_error(LJMD_EINVAL, "max_d2 is NULL");
+  if (n > 0 && (!x || !x_ref)) return set_error(LJMD_EINVAL, "x/x_ref is NULL");
+  if (n > 0 && x == x_ref) return set_error(LJMD_EINVAL, "x_ref must not alias x");
+  LJMD_TRY(check_ws(ws, ws_bytes, stream_workspace(n)));
+  return launch_max_displacement(make_box(box), n, x, x_ref, max_d2, ws, (hipStream_t)stream);
 }
 
 int ljmd_traj_loss(const ljmd_box *box, int64_t n, const double *x, const double *xref,

@@ -151,6 +151,52 @@ __global__ __launch_bounds__(kThreads) void k_gather_rows(int64_t n, int32_t wid
   if (t >= 0 && t < n) dst[q] = src[t * width + c];
 }
 
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Largest value over the block's threads into out (every thread calls it).
+__device__ __forceinline__ void block_max(double v, double *red, double *out) {
+  v = wave_max_f64(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int k = 1; k < (int)(blockDim.x / kWave); ++k) m = fmax(m, red[k]);
+    *out = m;
+  }
+}
+
+// Squared minimum-image displacement |x_i - xref_i|^2 of each atom (one thread per
+// atom), the block's largest into partial[block].
+__global__ __launch_bounds__(kThreads) void k_disp2_max(int64_t n, BoxK b,
+                                                        const double *__restrict__ x,
+                                                        const double *__restrict__ xref,
+                                                        double *__restrict__ partial) {
+  __shared__ double red[kThreads / kWave];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double d2 = 0.0;
+  if (i < n) {
+    const double dx = min_image(x[3 * i] - xref[3 * i], b.L[0], b.invL[0]);
+    const double dy = min_image(x[3 * i + 1] - xref[3 * i + 1], b.L[1], b.invL[1]);
+    const double dz = min_image(x[3 * i + 2] - xref[3 * i + 2], b.L[2], b.invL[2]);
+    d2 = dist2(dx, dy, dz);
+  }
+  block_max(d2, red, partial + blockIdx.x);
+}
+
+// Largest of m partial values (one block).
+__global__ __launch_bounds__(1024) void k_max_rows(int64_t m, const double *__restrict__ p,
+                                                   double *__restrict__ out) {
+  __shared__ double red[1024 / kWave];
+  double v = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += 1024) v = fmax(v, p[q]);
+  block_max(v, red, out);
+}
+
 inline unsigned nblocks(int64_t m) {
   const int64_t b = (m + kThreads - 1) / kThreads;
   return (unsigned)(b > 0 ? b : 1);
@@ -194,6 +240,15 @@ int launch_adjoint_kick(int64_t n, double dt, double w, const double *xbar, doub
   if (n > 0)
     k_adjoint_kick<<<nblocks(3 * n), kThreads, 0, st>>>(3 * n, dt, w * dt, xbar, vbar, g);
   return check_launch("ljmd_adjoint_kick");
+}
+
+int launch_max_displacement(const BoxK &b, int64_t n, const double *x, const double *xref,
+                            double *max_d2, void *ws, hipStream_t st) {
+  const unsigned nb = nblocks(n);
+  double *partial = (double *)ws;
+  if (n > 0) k_disp2_max<<<nb, kThreads, 0, st>>>(n, b, x, xref, partial);
+  k_max_rows<<<1, 1024, 0, st>>>(n > 0 ? nb : 0, partial, max_d2);
+  return check_launch("ljmd_max_displacement");
 }
 
 int launch_loss(const BoxK &b, int64_t n, const double *x, const double *xref, double *xbar,

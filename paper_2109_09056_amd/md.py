@@ -110,6 +110,7 @@ class LJSim:
         self.nl = NeighborList(self.L, self.rlist, kind, device=self.device)
         self.step_count = 0
         self._ws = {}
+        self.skin = float(skin)
 
     # ------------------------------------------------------------------ setup
     def load(self, x, v, types=None, ids=None):
@@ -142,13 +143,35 @@ class LJSim:
         self._ws[ops.OP_BIN] = torch.empty(
             max(ops.workspace_bytes(ops.OP_BIN, n, ncells=nc[0] * nc[1] * nc[2]), 8),
             dtype=torch.uint8, device=dev)
+        # dangerous-build check: positions at the last build, and per rebuild the largest
+        # squared displacement since then, kept on the device until thermo() reads them
+        self._ws[ops.OP_DISPLACEMENT] = torch.empty(
+            max(ops.workspace_bytes(ops.OP_DISPLACEMENT, n), 8), dtype=torch.uint8, device=dev)
+        self._xref = torch.empty_like(x)
+        self._have_ref = False
+        self._disp2 = torch.zeros(self.DISP_HISTORY, dtype=torch.float64, device=dev)
+        self._ndisp = 0
+        self._disp_seen = []
         self.rebuild()
         self.compute_forces(energy=True)
         ops.integrate(KINETIC, self.dt, self.mass, self.L, None, self.v, None, ke=self.ke,
                       ws=self._ws[ops.OP_INTEGRATE])
         return self
 
+    DISP_HISTORY = 4096
+
+    def _check_displacement(self):
+        """Largest squared displacement since the last build, into the device history."""
+        if self._ndisp == self.DISP_HISTORY:
+            self._disp_seen.extend(self._disp2.tolist())
+            self._ndisp = 0
+        ops.max_displacement(self.L, self.x, self._xref, out=self._disp2[self._ndisp:self._ndisp + 1],
+                             ws=self._ws[ops.OP_DISPLACEMENT])
+        self._ndisp += 1
+
     def rebuild(self):
+        if self._have_ref:
+            self._check_displacement()
         xo, vo, to, io, self.cell_start = ops.bin(
             self.L, self.rlist, self.x, self.v, self.types, self.ids, out=self._alt,
             cell_start=self.cell_start, ws=self._ws.get(ops.OP_BIN))
@@ -156,7 +179,21 @@ class LJSim:
                      self.ids if self.ids is not None else torch.empty_like(io))
         self.x, self.v, self.types, self.ids = xo, vo, to, io
         self.nl.build(self.x, self.cell_start)
+        self._xref.copy_(self.x)
+        self._have_ref = True
         self._fargs = {}
+
+    def displacement_history(self):
+        """Per rebuild so far, the largest displacement of any atom since the build before."""
+        return [math.sqrt(v) for v in self._disp_seen + self._disp2[:self._ndisp].tolist()]
+
+    def displacement_report(self):
+        """Dangerous-build check over every rebuild so far: a list of cutoff rc + skin
+        holds every pair inside rc only while no atom has moved more than skin/2 since
+        it was built.  Returns (windows checked, windows in which some atom moved more
+        than skin/2, the largest displacement seen)."""
+        d = self.displacement_history()
+        return len(d), sum(1 for v in d if v > 0.5 * self.skin), max(d) if d else 0.0
 
     # ------------------------------------------------------------------- step
     def compute_forces(self, energy=True):
@@ -341,8 +378,10 @@ class LJSim:
         vol = self.L[0] * self.L[1] * self.L[2]
         temp = 2.0 * ke / (3 * self.n - 3)
         press = (self.n * temp + float(ev[1] + ev[2] + ev[3]) / 3.0) / vol
+        checked, dangerous, dmax = self.displacement_report()
         return dict(step=self.step_count, pe=pe, ke=ke, etot=pe + ke, temp=temp, press=press,
-                    virial=ev[1:7].tolist(), builds=self.nl.builds, maxn=self.nl.maxn)
+                    virial=ev[1:7].tolist(), builds=self.nl.builds, maxn=self.nl.maxn,
+                    checked_builds=checked, dangerous_builds=dangerous, max_displacement=dmax)
 
     def in_caller_order(self, t):
         """Rows of a sorted-order tensor rearranged into the caller's atom order (ids)."""

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
                    MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
-                   OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_MD_CHAIN, OP_SPH, OP_SPME,
+                   OP_DISPLACEMENT, OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_MD_CHAIN,
+                   OP_SPH, OP_SPME,
                    SPME_MAX_GRID, TILE, LjmdError, make_box)
 
 
@@ -358,6 +359,25 @@ def adjoint_kick(dt, w, xbar, vbar, g):
         _need(t, name, torch.float64, (n, 3), dev)
     _lib.check(_lib.load().ljmd_adjoint_kick(n, float(dt), float(w), _ptr(xbar), _ptr(vbar),
                                              _ptr(g), _stream(dev)), "ljmd_adjoint_kick")
+
+
+def max_displacement(L, x, x_ref, out=None, ws=None):
+    """Largest squared minimum-image displacement max_i |x_i - x_ref_i|^2 (device scalar;
+    out: a one-element FP64 tensor, possibly a view into a longer buffer)."""
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(x_ref, "x_ref", torch.float64, (n, 3), dev)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    if out.device != dev or out.dtype != torch.float64 or out.numel() != 1:
+        raise ValueError("out must be one FP64 element on the device of x")
+    ws, need = _ws(OP_DISPLACEMENT, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_max_displacement(ctypes.byref(b), n, _ptr(x), _ptr(x_ref),
+                                                 _ptr(out), _ptr(ws), need, _stream(dev)),
+               "ljmd_max_displacement")
+    return out
 
 
 def traj_loss(L, x, xref, xbar=None, loss=None, ws=None):

@@ -239,3 +239,18 @@ def test_noalloc_step_limit_on_host(lib):
               fake, None)
     assert rc == lib.EWORKSPACE
     assert b"ljmd_md_step with a workspace" in lib.load().ljmd_last_error()
+
+
+def test_max_displacement_validation(lib):
+    L = lib.load()
+    b = lib.make_box((20.0, 20.0, 20.0))
+    fake, other = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    ws = L.ljmd_workspace_bytes(lib.OP_DISPLACEMENT, 1000, 0, 1)
+    assert ws >= 8 * (1000 // 256)
+    assert call(lib, "ljmd_max_displacement", ctypes.byref(b), 1000, fake, other, None, fake, ws,
+                None) == lib.EINVAL
+    assert call(lib, "ljmd_max_displacement", ctypes.byref(b), 1000, fake, fake, other, fake, ws,
+                None) == lib.EINVAL
+    assert b"alias" in L.ljmd_last_error()
+    assert call(lib, "ljmd_max_displacement", ctypes.byref(b), 1000, fake, other, other, fake, 8,
+                None) == lib.EWORKSPACE

@@ -334,3 +334,40 @@ def test_forces_at_oracle_snapshot(dev, orc, oracle_32k_run, snap, kind, prec):
         assert (np.abs(eg - eo) / np.abs(eo)).max() <= 1e-6
         assert ev[0] == pytest.approx(Eo, rel=1e-6)
         assert np.abs(ev[1:] - Wo).max() <= 1e-6 * np.abs(Wo).max()
+
+
+@pytest.mark.parametrize("every,steps", [(50, 100), (10, 40), (5, 40)])
+def test_dangerous_build_check_vs_oracle(dev, orc, every, steps):
+    """256-atom liquid with the list rebuilt every `every` steps: the largest displacement
+    of each window (checked on the GPU at every rebuild) equals the oracle's, from its
+    own trajectory, and every window in which the oracle's stale list misses pairs inside
+    rc is flagged (some atom moved more than skin/2); with a 50-step window the oracle
+    misses pairs, with 5 steps nothing is missed or flagged."""
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj256"]
+    s = li.make_system(w)
+    missed = []
+    rec = set(range(0, steps + 1, every))
+    _, _, _, _, snaps, _ = orc.run_nve(s["x"], s["v"], w.box, w.rc, w.rlist, w.dt, steps,
+                                       rebuild_every=every, record=rec, missed=missed)
+    sim = md.LJSim(w.box, precision=ops.FP64, rebuild_every=every, dt=w.dt, device=dev)
+    sim.load(s["x"], s["v"])
+    sim.step(steps)
+    got = sim.displacement_history()
+    assert len(got) == steps // every
+    flagged = 0
+    for k, dk in enumerate(got):
+        d = snaps[(k + 1) * every][0] - snaps[k * every][0]
+        d -= w.box * np.round(d / w.box)
+        want = np.sqrt((d * d).sum(axis=1)).max()
+        assert dk == pytest.approx(want, abs=1e-9)
+        miss = max(missed[k * every + 1:(k + 1) * every + 1])
+        if miss > 0:
+            assert dk > 0.5 * w.skin
+        flagged += dk > 0.5 * w.skin
+    checked, dangerous, dmax = sim.displacement_report()
+    assert (checked, dangerous) == (len(got), flagged) and dmax == max(got)
+    if every == 50:
+        assert max(missed) > 0 and dangerous == 2
+    if every == 5:
+        assert max(missed) == 0 and dangerous == 0
