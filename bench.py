@@ -260,7 +260,8 @@ def rebuild_time(sim, reps=20):
 def traversal_study(w, sim, reps=50):
     """Forces + energy/virial of the 500k workload (mixed) over the same pairs: the dense
     tiled list walked by two lanes per atom (the production kernel) against its CSR copy
-    walked by 1, 2, 4, 8 and 16 lanes per atom; plus the tiled -> CSR conversion."""
+    walked by 1, 2, 4, 8 and 16 lanes per atom, positions in AoSoA layouts (SoA, 8, 64),
+    and the half list; plus the tiled -> CSR conversion."""
     import torch
     from paper_2109_09056_amd import ops
     nl = sim.nl
@@ -273,6 +274,17 @@ def traversal_study(w, sim, reps=50):
     ev = torch.empty(7, dtype=torch.float64, device=sim.device)
     out = {"list_to_csr_us": round(event_time(lambda: ops.list_to_csr(
         nl.nbr, nl.nnbr, nl.maxn, cap=cap, offsets=off, csr=csr, ws=wsc), reps) * 1e3, 2)}
+    # building the lists: tiled (the production build) and CSR straight from the cells
+    wsb = torch.empty(ops.workspace_bytes(ops.OP_BUILD_CSR, sim.n), dtype=torch.uint8,
+                      device=sim.device)
+    off2 = torch.empty_like(off)
+    csr2 = torch.empty(cap + 64, dtype=torch.int32, device=sim.device)
+    out["build_tiled_us"] = round(event_time(lambda: ops.build_neighbors(
+        w.box, sim.rlist, ops.FULL, sim.x, sim.cell_start, nl.maxn, nl.nbr, nl.nnbr,
+        nl.max_count), reps) * 1e3, 2)
+    out["build_csr_direct_us"] = round(event_time(lambda: ops.build_neighbors_csr(
+        w.box, sim.rlist, ops.FULL, sim.x, sim.cell_start, cap=csr2.numel(), offsets=off2,
+        csr=csr2, ws=wsb), reps) * 1e3, 2)
     out["tiled_team2_us"] = round(event_time(lambda: ops.compute_forces(
         w.box, ops.MIXED, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
         nl.nnbr, nl.maxn, F=F, e_atom=e, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
@@ -280,6 +292,27 @@ def traversal_study(w, sim, reps=50):
         out[f"csr_team{team}_us"] = round(event_time(lambda: ops.compute_forces_csr(
             w.box, ops.MIXED, w.rc, sim.eps, sim.sigma, sim.x, sim.types, off, csr, team=team,
             F=F, e_atom=e, ev=ev, ws=wsf), reps) * 1e3, 2)
+    # positions and forces in AoSoA(V) layouts (0: SoA) over the same tiled list, team 2
+    for vlen in (0, 8, 64):
+        xa = ops.aosoa_convert(sim.x, vlen, True)
+        Fa = torch.empty_like(xa)
+        out[f"aosoa_v{vlen}_us"] = round(event_time(lambda: ops.compute_forces_aosoa(
+            w.box, ops.MIXED, w.rc, sim.eps, sim.sigma, xa, sim.types, nl.nbr, nl.nnbr,
+            nl.maxn, vlen, F=Fa, e_atom=e, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+    # half list (each pair once, j-side sums through LDS tiles and atomics), same positions
+    from paper_2109_09056_amd import md
+    hl = md.NeighborList(sim.L, sim.rlist, ops.HALF, device=sim.device).build(sim.x,
+                                                                            sim.cell_start)
+    for name, ea in (("half_list_us", e), ("half_list_no_eatom_us", None)):
+        out[name] = round(event_time(lambda: ops.compute_forces(
+            w.box, ops.MIXED, ops.HALF, w.rc, sim.eps, sim.sigma, sim.x, sim.types, hl.nbr,
+            hl.nnbr, hl.maxn, F=F, e_atom=ea, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+    out["tiled_team2_forces_only_us"] = round(event_time(lambda: ops.compute_forces(
+        w.box, ops.MIXED, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
+        nl.nnbr, nl.maxn, F=F, want_energy=False, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+    out["half_list_forces_only_us"] = round(event_time(lambda: ops.compute_forces(
+        w.box, ops.MIXED, ops.HALF, w.rc, sim.eps, sim.sigma, sim.x, sim.types, hl.nbr,
+        hl.nnbr, hl.maxn, F=F, want_energy=False, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
     return out
 
 

@@ -19,8 +19,10 @@
  *   ljmd_md_step_chained, ljmd_md_step_sums
  *                         the same step with its energy sums formed during the
  *                         next step's launch (one launch per step)
- *   ljmd_list_to_csr, ljmd_compute_forces_csr
+ *   ljmd_build_neighbors_csr, ljmd_list_to_csr, ljmd_compute_forces_csr
  *                         compressed list form and team-per-atom traversal
+ *   ljmd_compute_forces_aosoa, ljmd_aosoa_convert
+ *                         forces with positions in AoSoA layouts
  *   ljmd_force_backward   vector-Jacobian product of the forces (adjoint)
  *   ljmd_sph_density, ljmd_sph_accel, ljmd_sph_accel_step
  *                         SPH density summation and pressure acceleration over
@@ -95,6 +97,7 @@ extern "C" {
 #define LJMD_OP_SPME 9       /* ljmd_spme_recip; ncells = K[0]*K[1]*K[2] grid points */
 #define LJMD_OP_MD_CHAIN 10  /* ljmd_md_step_chained, ljmd_md_step_sums (two halves) */
 #define LJMD_OP_DISPLACEMENT 11 /* ljmd_max_displacement */
+#define LJMD_OP_BUILD_CSR 12    /* ljmd_build_neighbors_csr */
 #define LJMD_SPME_MAX_GRID 256 /* largest grid edge of ljmd_spme_recip */
 
 #define LJMD_MAX_TYPES 8
@@ -172,6 +175,25 @@ int ljmd_build_neighbors(const ljmd_box *box, double rlist, int kind, int64_t n,
                          int32_t *nbr, int32_t *nnbr, int32_t *max_count, void *stream);
 
 /*
+ * ljmd_build_neighbors_csr -- the same lists as ljmd_build_neighbors, built
+ * straight into compressed (CSR) storage (paper: Cabana "Neighbor List
+ * Creation" -- compressed lists, row offsets plus one flat index array, built
+ * from the binning grid): a counting pass over the stencil, an exclusive scan
+ * of the row lengths, then a filling pass.  Row order as ljmd_build_neighbors'
+ * for the same kind.
+ *   offsets  int64 [n+1] output: row i is nbr[offsets[i] .. offsets[i+1]);
+ *            offsets[n] = total entries
+ *   nbr      int32 [cap] output; entries at positions >= cap are not written,
+ *            so a too-small cap is seen as offsets[n] > cap once the call
+ *            completes (the caller builds again with cap >= offsets[n])
+ *   ws       >= ljmd_workspace_bytes(LJMD_OP_BUILD_CSR, n, 0, 0)
+ * Other arguments and errors as in ljmd_build_neighbors.
+ */
+int ljmd_build_neighbors_csr(const ljmd_box *box, double rlist, int kind, int64_t n,
+                             const double *x, const int32_t *cell_start, int64_t *offsets,
+                             int32_t *nbr, int64_t cap, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * ljmd_compute_forces -- 12-6 Lennard-Jones forces over the neighbor list
  * (paper: CabanaMD's Lennard-Jones short-range force kernel, written as a
  * neighbor parallel loop; Introduction: per-particle forces from the
@@ -219,6 +241,35 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
 int ljmd_integrate(int stage, double dt, double mass, const ljmd_box *box, int64_t n,
                    double *x, double *v, const double *F, double *ke, void *ws,
                    size_t ws_bytes, void *stream);
+
+/*
+ * ljmd_compute_forces_aosoa -- ljmd_compute_forces on a FULL list with positions
+ * and forces in an AoSoA(vlen) layout (paper: Cabana "Particle abstractions:
+ * data structures" -- arrays of structs of arrays with a vector length; the
+ * CabanaMD LJ kernel is the vehicle for its layout studies).  Layout: chunks of
+ * vlen consecutive atoms, each holding its x's, then its y's, then its z's;
+ * the last chunk holds the m = n mod vlen remaining atoms (when nonzero) the
+ * same way, so the array is exactly 3n doubles.  Component k of atom i, in
+ * chunk c = i / vlen of width w = min(vlen, n - c*vlen), is at
+ * c*3*vlen + k*w + (i - c*vlen).
+ *   vlen     1 (the [n][3] arrays of every other call), 8, 64, or 0 for plain
+ *            SoA (component k of atom i at k*n + i); n <= 2^24 unless vlen = 1
+ *   x        [3n] positions in that layout; F [3n] output forces in it
+ * Same list traversal and summation order as ljmd_compute_forces: forces,
+ * energies and virial are bitwise the same in every layout.  Other arguments,
+ * workspace (LJMD_OP_FORCES) and errors as in ljmd_compute_forces.
+ */
+int ljmd_compute_forces_aosoa(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                              const double *eps_packed, const double *sigma_packed, int64_t n,
+                              int32_t vlen, const double *x, const int32_t *type,
+                              const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double *F,
+                              double *e_atom, double *ev, void *ws, size_t ws_bytes,
+                              void *stream);
+
+/* Rearranges [n][3] rows into AoSoA(vlen) (to_aosoa = 1) or back (0); src and
+ * dst must not alias.  vlen as in ljmd_compute_forces_aosoa. */
+int ljmd_aosoa_convert(int64_t n, int32_t vlen, int to_aosoa, const double *src, double *dst,
+                       void *stream);
 
 /*
  * ljmd_force_backward -- adjoint of ljmd_compute_forces (FULL list only).

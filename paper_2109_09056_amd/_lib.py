@@ -18,7 +18,7 @@ FP64, MIXED = 0, 1
 FULL, HALF = 0, 1
 KICK_DRIFT, KICK, KINETIC, KICK_KICK_DRIFT = 0, 1, 2, 3
 (OP_BIN, OP_FORCES, OP_BACKWARD, OP_INTEGRATE, OP_LOSS, OP_CSR, OP_FORCES_CSR, OP_SPH,
- OP_EWALD_REAL, OP_SPME, OP_MD_CHAIN, OP_DISPLACEMENT) = range(12)
+ OP_EWALD_REAL, OP_SPME, OP_MD_CHAIN, OP_DISPLACEMENT, OP_BUILD_CSR) = range(13)
 SPME_MAX_GRID = 256
 MAX_TYPES = 8
 TILE = 64
@@ -47,6 +47,8 @@ SIGNATURES = {
     "ljmd_last_error": (ctypes.c_char_p, []),
     "ljmd_bin": (_int, [_box, _dbl, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _sz, _p]),
     "ljmd_build_neighbors": (_int, [_box, _dbl, _int, _i64, _p, _p, _i32, _p, _p, _p, _p]),
+    "ljmd_build_neighbors_csr": (_int, [_box, _dbl, _int, _i64, _p, _p, _p, _p, _i64, _p, _sz,
+                                        _p]),
     "ljmd_compute_forces": (_int, [_box, _int, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p,
                                    _i32, _p, _p, _p, _p, _sz, _p]),
     "ljmd_integrate": (_int, [_int, _dbl, _dbl, _box, _i64, _p, _p, _p, _p, _p, _sz, _p]),
@@ -62,6 +64,9 @@ SIGNATURES = {
     "ljmd_list_to_csr": (_int, [_i64, _p, _p, _i32, _p, _p, _i64, _p, _sz, _p]),
     "ljmd_compute_forces_csr": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _p, _p, _p, _p,
                                        _i32, _p, _p, _p, _p, _sz, _p]),
+    "ljmd_compute_forces_aosoa": (_int, [_box, _int, _dbl, _i32, _p, _p, _i64, _i32, _p, _p,
+                                         _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
+    "ljmd_aosoa_convert": (_int, [_i64, _i32, _int, _p, _p, _p]),
     "ljmd_sph_density": (_int, [_box, _dbl, _dbl, _dbl, _dbl, _i64, _p, _p, _p, _i32, _p, _p,
                                 _p, _sz, _p]),
     "ljmd_sph_accel": (_int, [_box, _dbl, _dbl, _dbl, _dbl, _i64, _p, _p, _p, _p, _i32, _p, _p,

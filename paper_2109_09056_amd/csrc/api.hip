@@ -15,6 +15,10 @@ size_t bin_workspace(int64_t n, int64_t ncells);
 int launch_bin(const GridK &g, int64_t n, const double *x_in, const double *v_in,
                const int32_t *type_in, const int64_t *id_in, double *x_out, double *v_out,
                int32_t *type_out, int64_t *id_out, int32_t *cell_start, void *ws, hipStream_t st);
+size_t build_csr_workspace(int64_t n);
+int launch_build_csr(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n,
+                     const double *x, const int32_t *cell_start, int64_t *offsets, int32_t *csr,
+                     int64_t cap, void *ws, hipStream_t st);
 int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n, const double *x,
                  const int32_t *cell_start, int32_t maxn, int32_t *nbr, int32_t *nnbr,
                  int32_t *max_count, hipStream_t st);
@@ -30,6 +34,13 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
                    double *v, double *x_next, int open_next, double *F, double *e_atom, double *ev,
                    double *partial, const double *prev_partial, double *prev_ev, hipStream_t st);
 int launch_md_step_sums(int64_t n, const double *partial, double *ev, hipStream_t st);
+int launch_forces_aosoa(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                        const double *sig, int64_t n, int vlen, const double *x,
+                        const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
+                        int32_t maxn, double *F, double *e_atom, double *ev, void *ws,
+                        hipStream_t st);
+int launch_aosoa_convert(int64_t n, int vlen, int to_aosoa, const double *src, double *dst,
+                         hipStream_t st);
 size_t bwd_workspace(int64_t n, int32_t ntypes);
 int launch_backward(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
                     const double *sig, int64_t n, const double *x, const int32_t *type,
@@ -259,6 +270,7 @@ size_t ljmd_workspace_bytes(int op, int64_t n, int64_t ncells, int32_t ntypes) {
     case LJMD_OP_INTEGRATE:
     case LJMD_OP_LOSS:
     case LJMD_OP_DISPLACEMENT: return stream_workspace(n);
+    case LJMD_OP_BUILD_CSR: return build_csr_workspace(n);
     case LJMD_OP_CSR: return csr_workspace(n);
     case LJMD_OP_FORCES_CSR: return csr_force_workspace(n);
     case LJMD_OP_SPH: return sph_workspace(n);
@@ -309,6 +321,23 @@ int ljmd_build_neighbors(const ljmd_box *box, double rlist, int kind, int64_t n,
                       (hipStream_t)stream);
 }
 
+int ljmd_build_neighbors_csr(const ljmd_box *box, double rlist, int kind, int64_t n,
+                             const double *x, const int32_t *cell_start, int64_t *offsets,
+                             int32_t *nbr, int64_t cap, void *ws, size_t ws_bytes, void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rlist, "rlist"));
+  LJMD_TRY(check_n(n));
+  if (kind != LJMD_FULL && kind != LJMD_HALF) return set_error(LJMD_EINVAL, "bad kind %d", kind);
+  if (!cell_start || !offsets) return set_error(LJMD_EINVAL, "cell_start/offsets is NULL");
+  if (cap < 0) return set_error(LJMD_EINVAL, "cap = %lld must be >= 0", (long long)cap);
+  if (n > 0 && (!x || (cap > 0 && !nbr))) return set_error(LJMD_EINVAL, "x/nbr is NULL");
+  LJMD_TRY(check_ws(ws, ws_bytes, build_csr_workspace(n)));
+  GridK g;
+  LJMD_TRY(make_grid(box, rlist, &g));
+  return launch_build_csr(g, make_box(box), rlist, kind, n, x, cell_start, offsets, nbr, cap, ws,
+                          (hipStream_t)stream);
+}
+
 int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
                         int32_t ntypes, const double *eps_packed, const double *sigma_packed,
                         int64_t n, const double *x, const int32_t *type, const int32_t *nbr,
@@ -327,6 +356,47 @@ int ljmd_compute_forces(const ljmd_box *box, int precision, int kind, double rc,
   LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? force_workspace(n) : 0));
   return launch_forces(make_box(box), precision, kind, rc, ntypes, eps_packed, sigma_packed, n, x,
                        type, nbr, nnbr, maxn, F, e_atom, ev, ws, (hipStream_t)stream);
+}
+
+static int check_vlen(int32_t vlen) {
+  if (vlen != 0 && vlen != 1 && vlen != 8 && vlen != 64)
+    return set_error(LJMD_EINVAL, "vlen = %d must be 0 (SoA), 1, 8 or 64", vlen);
+  return LJMD_OK;
+}
+
+int ljmd_compute_forces_aosoa(const ljmd_box *box, int precision, double rc, int32_t ntypes,
+                              const double *eps_packed, const double *sigma_packed, int64_t n,
+                              int32_t vlen, const double *x, const int32_t *type,
+                              const int32_t *nbr, const int32_t *nnbr, int32_t maxn, double *F,
+                              double *e_atom, double *ev, void *ws, size_t ws_bytes,
+                              void *stream) {
+  LJMD_TRY(check_box(box));
+  LJMD_TRY(check_cutoff(box, rc, "rc"));
+  LJMD_TRY(check_n(n));
+  LJMD_TRY(check_vlen(vlen));
+  if (precision != LJMD_FP64 && precision != LJMD_MIXED)
+    return set_error(LJMD_EINVAL, "bad precision %d", precision);
+  LJMD_TRY(check_params(ntypes, eps_packed, sigma_packed, type, n));
+  if (maxn < 1) return set_error(LJMD_EINVAL, "maxn = %d must be >= 1", maxn);
+  if (n > 0 && (!x || !nbr || !nnbr || !F)) return set_error(LJMD_EINVAL, "x/nbr/nnbr/F is NULL");
+  if (n > kNarrowAtoms && vlen != 1)
+    return set_error(LJMD_EINVAL, "AoSoA layouts take at most %lld atoms", (long long)kNarrowAtoms);
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  LJMD_TRY(check_ws(ws, ws_bytes, want_ev ? force_workspace(n) : 0));
+  return launch_forces_aosoa(make_box(box), precision, rc, ntypes, eps_packed, sigma_packed, n,
+                             vlen, x, type, nbr, nnbr, maxn, F, e_atom, ev, ws,
+                             (hipStream_t)stream);
+}
+
+int ljmd_aosoa_convert(int64_t n, int32_t vlen, int to_aosoa, const double *src, double *dst,
+                       void *stream) {
+  LJMD_TRY(check_n(n));
+  LJMD_TRY(check_vlen(vlen));
+  if (to_aosoa != 0 && to_aosoa != 1)
+    return set_error(LJMD_EINVAL, "to_aosoa = %d must be 0 or 1", to_aosoa);
+  if (n > 0 && (!src || !dst)) return set_error(LJMD_EINVAL, "src/dst is NULL");
+  if (n > 0 && src == dst) return set_error(LJMD_EINVAL, "dst must not alias src");
+  return launch_aosoa_convert(n, vlen, to_aosoa, src, dst, (hipStream_t)stream);
 }
 
 static int check_sph(const ljmd_box *box, double h, double mass, double c0, double rho0, int64_t n,

@@ -102,9 +102,55 @@ __global__ __launch_bounds__(kThreads) void k_fill(int64_t n, const int32_t *__r
   }
 }
 
+// offsets[i] = sum of counts over atoms before i, per chunk (local exclusive scan
+// plus the chunk's prefix).
+__global__ __launch_bounds__(kThreads) void k_offsets(int64_t n, const int32_t *__restrict__ cnt,
+                                                      const int64_t *__restrict__ chunk_prefix,
+                                                      int64_t *__restrict__ offsets) {
+  __shared__ int64_t buf[kThreads];
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  int32_t c[kPerThread];
+  int64_t own = 0;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int64_t i = base + (int64_t)threadIdx.x * kPerThread + q;
+    c[q] = i < n ? cnt[i] : 0;
+    own += c[q];
+  }
+  buf[threadIdx.x] = own;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const int64_t o = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += o;
+    __syncthreads();
+  }
+  int64_t pos = chunk_prefix[blockIdx.x] + buf[threadIdx.x] - own;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int64_t i = base + (int64_t)threadIdx.x * kPerThread + q;
+    if (i < n) offsets[i] = pos;
+    pos += c[q];
+  }
+}
+
 int64_t nchunks(int64_t n) { return n > 0 ? (n + kChunk - 1) / kChunk : 1; }
 
 }  // namespace
+
+// Exclusive scan of row lengths: offsets[i] (i < n) and offsets[n] = the total.
+int launch_offsets(int64_t n, const int32_t *counts, int64_t *offsets, void *ws, hipStream_t st) {
+  const int64_t nc = nchunks(n);
+  int64_t *chunk = (int64_t *)ws;
+  if (n > 0) {
+    k_chunk_sums<<<(unsigned)nc, kThreads, 0, st>>>(n, counts, INT32_MAX, chunk);
+    k_scan_chunks<<<1, kThreads, 0, st>>>(nc, chunk, offsets + n);
+    k_offsets<<<(unsigned)nc, kThreads, 0, st>>>(n, counts, chunk, offsets);
+  } else {
+    k_scan_chunks<<<1, kThreads, 0, st>>>(0, chunk, offsets);
+  }
+  return check_launch("row offsets");
+}
 
 size_t csr_workspace(int64_t n) { return (size_t)(nchunks(n) + 1) * sizeof(int64_t); }
 

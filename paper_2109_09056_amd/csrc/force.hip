@@ -204,6 +204,55 @@ __device__ __forceinline__ void add_xf(double xi, double yi, double zi, Acc &s) 
   s.wyz = __builtin_fma(y2, s.fz, s.wyz);
 }
 
+// Positions and forces in an AoSoA(V) layout (Cabana's array of structs of
+// arrays): chunks of V consecutive atoms, each chunk holding its x's, then its
+// y's, then its z's; the last chunk holds the m = n mod V remaining atoms (when
+// nonzero) in the same way, so the array is exactly 3n long.  V = 1 is [n][3];
+// V = 0 stands for plain SoA (three arrays of n).  Component k of atom i sits
+// at aos_index<V>(i, k, n).
+template <int V>
+__device__ __forceinline__ int64_t aos_width(int64_t c, int64_t n) {  // atoms in chunk c
+  const int64_t left = n - c * V;
+  return left < V ? left : V;
+}
+
+template <int V>
+__device__ __forceinline__ int64_t aos_index(int64_t i, int k, int64_t n) {
+  if constexpr (V == 0) {
+    return k * n + i;
+  } else if constexpr (V == 1) {
+    return 3 * i + k;
+  } else {
+    const int64_t c = i / V;
+    return c * (3 * V) + k * aos_width<V>(c, n) + (i - c * V);
+  }
+}
+
+// Atom j's position: V = 1 as a 16-byte and an 8-byte load (pos_of); other
+// layouts as three 8-byte loads.
+template <int V, bool WIDE>
+__device__ __forceinline__ void load_pos(const double *x, int32_t j, int64_t n, double &xj,
+                                         double &yj, double &zj) {
+  if constexpr (V == 1) {
+    const double *p = pos_of<WIDE>(x, j);
+    xj = p[0];
+    yj = p[1];
+    zj = p[2];
+  } else if constexpr (V == 0) {
+    const double *p = x + j;
+    xj = p[0];
+    yj = p[n];
+    zj = p[2 * n];
+  } else {
+    const int64_t c = j / V;
+    const int64_t m = aos_width<V>(c, n);
+    const double *p = x + c * (3 * V) + (j - c * V);
+    xj = p[0];
+    yj = p[m];
+    zj = p[2 * m];
+  }
+}
+
 // Walk atom i's row in groups of U slots: the U index loads, then the U
 // position gathers, then the U pair evaluations, so several loads are in
 // flight per lane.  Whole groups read their indices at fixed offsets from one
@@ -216,7 +265,7 @@ __device__ __forceinline__ void add_xf(double xi, double yi, double zi, Acc &s) 
 // where any pair closer than rc has the same raw and minimum-image
 // displacement, and any other pair has some |raw component| above L/2 > rc
 // and is rejected by the cutoff test either way.
-template <bool MIXED, bool T1, bool EV, int U, bool WRAP, bool WIDE, int STRIDE = 1>
+template <bool MIXED, bool T1, bool EV, int U, bool WRAP, bool WIDE, int STRIDE = 1, int V = 1>
 __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row, int32_t cnt,
                                          double xi, double yi, double zi, int ti,
                                          const Coef &c1, const double *tab, Acc &s) {
@@ -230,10 +279,7 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
     double xj[U], yj[U], zj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double *p = pos_of<WIDE>(a.x, j[u]);
-      xj[u] = p[0];
-      yj[u] = p[1];
-      zj[u] = p[2];
+      load_pos<V, WIDE>(a.x, j[u], a.n, xj[u], yj[u], zj[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -251,10 +297,7 @@ __device__ __forceinline__ void walk_row(const ForceArgs &a, const int32_t *row,
       yj[u] = yi;
       zj[u] = zi;
       if (k + u < cnt) {  // no gathers for the padding slots
-        const double *p = pos_of<WIDE>(a.x, j[u]);
-        xj[u] = p[0];
-        yj[u] = p[1];
-        zj[u] = p[2];
+        load_pos<V, WIDE>(a.x, j[u], a.n, xj[u], yj[u], zj[u]);
       }
     }
 #pragma unroll
@@ -314,8 +357,10 @@ __device__ void block_colsum(const double *__restrict__ p, int64_t rows, double 
   }
 }
 
-template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE, int TEAM>
+template <bool MIXED, bool T1, bool EV, int U, bool SKIP, bool STEP, bool WIDE, int TEAM,
+          int V = 1>
 __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a) {
+  static_assert(!STEP || V == 1, "the fused step works on [n][3] arrays");
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
   __shared__ double red[kForceWaves * TEAM * 8];
   if constexpr (STEP) {
@@ -339,9 +384,9 @@ __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a
   const bool live = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0;
   if (live) {
-    xi = a.x[3 * (int64_t)i];
-    yi = a.x[3 * (int64_t)i + 1];
-    zi = a.x[3 * (int64_t)i + 2];
+    xi = a.x[aos_index<V>(i, 0, a.n)];
+    yi = a.x[aos_index<V>(i, 1, a.n)];
+    zi = a.x[aos_index<V>(i, 2, a.n)];
   }
   bool interior = false;
   if constexpr (SKIP) {
@@ -357,9 +402,9 @@ __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a
     const int32_t *row =
         a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
     if (SKIP && interior)
-      walk_row<MIXED, T1, EV, U, false, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+      walk_row<MIXED, T1, EV, U, false, WIDE, TEAM, V>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     else
-      walk_row<MIXED, T1, EV, U, true, WIDE, TEAM>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
+      walk_row<MIXED, T1, EV, U, true, WIDE, TEAM, V>(a, row, cnt, xi, yi, zi, ti, c1, tab, s);
     if constexpr (EV) add_xf(xi, yi, zi, s);
   }
   const double e_lane = s.e;
@@ -375,9 +420,9 @@ __global__ __launch_bounds__(kForceThreads * TEAM) void k_force_full(ForceArgs a
   if (live) {
     if (t == 0) {
       if (!STEP || a.F) {
-        a.F[3 * (int64_t)i] = s.fx;
-        a.F[3 * (int64_t)i + 1] = s.fy;
-        a.F[3 * (int64_t)i + 2] = s.fz;
+        a.F[aos_index<V>(i, 0, a.n)] = s.fx;
+        a.F[aos_index<V>(i, 1, a.n)] = s.fy;
+        a.F[aos_index<V>(i, 2, a.n)] = s.fz;
       }
       if (a.e_atom) a.e_atom[i] = 0.5 * s.e;
     }
@@ -419,73 +464,241 @@ __global__ void k_zero_f64(double *p, int64_t m) {
   if (q < m) p[q] = 0.0;
 }
 
-template <bool MIXED, bool T1, bool EV>
-__global__ __launch_bounds__(kForceThreads) void k_force_half(ForceArgs a) {
+// Half list (HALF): blocks of ATOMS consecutive sorted atoms, kHalfTeam lanes
+// per atom (lane t takes the row entries t, t + kHalfTeam, ...).  The owner of
+// pair (i, j), j > i, keeps +s*d for F_i in registers and hands -s*d (and u/2
+// for e_j) to j through LDS: the block's j-side sums are kept per 64-atom tile
+// of sorted atoms, in SLOTS slots assigned at a tile's first touch by a small
+// open-addressing table keyed by the tile; after the rows, each slot is added
+// to F (and e_atom) with coalesced FP64 atomics, one per touched atom and
+// component.  A pair whose tile finds no slot (more tiles than slots, or a slot
+// another wave has claimed but not yet published) adds its j-side through
+// direct global atomics.  Summation order is not fixed: HALF results are
+// reproducible to rounding, not bitwise.
+constexpr int kHalfTeam = 2;  // lanes per home atom
+constexpr int kHalfTabBits = 7;
+constexpr int kHalfTab = 1 << kHalfTabBits;  // table entries
+
+template <int NV, int SLOTS>
+struct HalfLds {
+  double acc[SLOTS][NV][kWave];  // per slot: Fx, Fy, Fz (, e) of the tile's 64 atoms
+  int32_t key[kHalfTab];          // tile, or -1
+  int32_t slot[kHalfTab];         // its slot, or -1 (none, or not yet published)
+  int32_t tile_of[SLOTS];
+  int32_t count;                  // slots claimed (may exceed SLOTS)
+};
+
+// Slot of `tile` in the block's table, claiming one at its first touch; -1 when
+// there is none to use (table or slots full, or claimed by another lane whose
+// publication this lane does not see yet).
+template <int NV, int SLOTS>
+__device__ __forceinline__ int32_t half_slot(HalfLds<NV, SLOTS> &s, int32_t tile) {
+  uint32_t h = ((uint32_t)tile * 2654435761u) >> (32 - kHalfTabBits);
+  for (int p = 0; p < kHalfTab; ++p) {
+    const int32_t k = __atomic_load_n(&s.key[h], __ATOMIC_RELAXED);
+    if (k == tile) return __atomic_load_n(&s.slot[h], __ATOMIC_RELAXED);
+    if (k < 0) {
+      const int32_t old = atomicCAS(&s.key[h], -1, tile);
+      if (old < 0) {
+        const int32_t q = atomicAdd(&s.count, 1);
+        const int32_t v = q < SLOTS ? q : -1;
+        if (v >= 0) s.tile_of[v] = tile;
+        __atomic_store_n(&s.slot[h], v, __ATOMIC_RELAXED);
+        return v;
+      }
+      if (old == tile) return __atomic_load_n(&s.slot[h], __ATOMIC_RELAXED);
+    }
+    h = (h + 1) & (kHalfTab - 1);
+  }
+  return -1;
+}
+
+// Row accumulators of the half-list kernel (per-pair virial, as the pair is seen once).
+struct HalfAcc {
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+};
+
+// EV: energy and virial sums; EATOM: per-atom energies (j-side halves through LDS).
+template <bool MIXED, bool T1, bool EV, bool EATOM, bool WRAP, int NV, int SLOTS>
+__device__ __forceinline__ void half_pair(const ForceArgs &a, HalfLds<NV, SLOTS> &s,
+                                          double xi, double yi, double zi, double xj, double yj,
+                                          double zj, int32_t j, bool valid, int ti,
+                                          const Coef &c1, const double *tab, HalfAcc &r,
+                                          int32_t &ltile, int32_t &lslot) {
+  double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  if constexpr (WRAP) {
+    dx = min_image(dx, a.b.L[0], a.b.invL[0]);
+    dy = min_image(dy, a.b.L[1], a.b.invL[1]);
+    dz = min_image(dz, a.b.L[2], a.b.invL[2]);
+  }
+  const double r2 = dist2(dx, dy, dz);
+  if (valid && r2 < a.rc2) {
+    Coef c;
+    if constexpr (T1) {
+      c = c1;
+    } else {
+      const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
+      c = Coef{t[0], t[1], t[2], t[3]};
+    }
+    const PairOut p = lj_pair<MIXED, EV || EATOM>(dx, dy, dz, r2, c);
+    r.fx += p.fx;
+    r.fy += p.fy;
+    r.fz += p.fz;
+    if constexpr (EV || EATOM) r.e += p.u;
+    if constexpr (EV) {
+      r.wxx = __builtin_fma(dx, p.fx, r.wxx);
+      r.wyy = __builtin_fma(dy, p.fy, r.wyy);
+      r.wzz = __builtin_fma(dz, p.fz, r.wzz);
+      r.wxy = __builtin_fma(dx, p.fy, r.wxy);
+      r.wxz = __builtin_fma(dx, p.fz, r.wxz);
+      r.wyz = __builtin_fma(dy, p.fz, r.wyz);
+    }
+    const int32_t tile = j >> 6;
+    if (tile != ltile || lslot < 0) {
+      lslot = half_slot(s, tile);
+      ltile = tile;
+    }
+    if (lslot >= 0) {
+      const int l = j & (kWave - 1);
+      unsafeAtomicAdd(&s.acc[lslot][0][l], -p.fx);
+      unsafeAtomicAdd(&s.acc[lslot][1][l], -p.fy);
+      unsafeAtomicAdd(&s.acc[lslot][2][l], -p.fz);
+      if constexpr (EATOM) unsafeAtomicAdd(&s.acc[lslot][NV - 1][l], 0.5 * p.u);
+    } else {
+      unsafeAtomicAdd(&a.F[3 * (int64_t)j], -p.fx);
+      unsafeAtomicAdd(&a.F[3 * (int64_t)j + 1], -p.fy);
+      unsafeAtomicAdd(&a.F[3 * (int64_t)j + 2], -p.fz);
+      if constexpr (EATOM) unsafeAtomicAdd(&a.e_atom[j], 0.5 * p.u);
+    }
+  }
+}
+
+// One lane's share of a half row: every kHalfTeam-th entry from `row`, in
+// groups of U (indices, then gathers, then pairs, as walk_row).
+template <bool MIXED, bool T1, bool EV, bool EATOM, bool WRAP, bool WIDE, int U, int NV,
+          int SLOTS>
+__device__ __forceinline__ void half_row(const ForceArgs &a, HalfLds<NV, SLOTS> &s,
+                                         const int32_t *row, int32_t cnt, double xi, double yi,
+                                         double zi, int ti, const Coef &c1, const double *tab,
+                                         HalfAcc &r) {
+  constexpr int kStep = kHalfTeam * kWave;
+  int32_t ltile = -1, lslot = -1;
+  for (int32_t k = 0; k < cnt; k += U, row += U * kStep) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = row[(k + u < cnt ? u : 0) * kStep];
+    double xj[U], yj[U], zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xj[u] = xi;
+      yj[u] = yi;
+      zj[u] = zi;
+      if (k + u < cnt) {
+        const double *q = pos_of<WIDE>(a.x, j[u]);
+        xj[u] = q[0];
+        yj[u] = q[1];
+        zj[u] = q[2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      half_pair<MIXED, T1, EV, EATOM, WRAP>(a, s, xi, yi, zi, xj[u], yj[u], zj[u], j[u],
+                                            k + u < cnt, ti, c1, tab, r, ltile, lslot);
+  }
+}
+
+template <bool MIXED, bool T1, bool EV, bool EATOM, bool WIDE, int ATOMS, int SLOTS, int U>
+__global__ __launch_bounds__(ATOMS * kHalfTeam) void k_force_half(ForceArgs a) {
+  constexpr int NV = EATOM ? 4 : 3;
+  constexpr int kThreads = ATOMS * kHalfTeam;
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ HalfLds<NV, SLOTS> s;
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
-  __shared__ double red[kForceWaves * 7];
-  Coef c1;
+  __shared__ double red[kWaves * 7];
+  for (int q = threadIdx.x; q < SLOTS * NV * kWave; q += kThreads) (&s.acc[0][0][0])[q] = 0.0;
+  for (int q = threadIdx.x; q < kHalfTab; q += kThreads) {
+    s.key[q] = -1;
+    s.slot[q] = -1;
+  }
+  if (threadIdx.x == 0) s.count = 0;
+  Coef c1{};
   if constexpr (T1) {
     c1 = coef_of(a.eps, a.sig, 0);
   } else {
-    load_table(a, tab);
+    load_table(a, tab);  // ends with a barrier
   }
-  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kForceThreads + threadIdx.x;
-  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-  double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
-  if (i < a.n) {
-    const double xi = a.x[3 * (int64_t)i], yi = a.x[3 * (int64_t)i + 1],
-                 zi = a.x[3 * (int64_t)i + 2];
+  __syncthreads();
+  const int t = (int)threadIdx.x % kHalfTeam;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * ATOMS + (int)threadIdx.x / kHalfTeam;
+  const bool live = i < a.n;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = a.x[3 * (int64_t)i];
+    yi = a.x[3 * (int64_t)i + 1];
+    zi = a.x[3 * (int64_t)i + 2];
+  }
+  const double m = a.rc;
+  const bool in = !live || (xi >= m && xi <= a.b.L[0] - m && yi >= m && yi <= a.b.L[1] - m &&
+                            zi >= m && zi <= a.b.L[2] - m);
+  const bool interior = __ballot(!in) == 0;  // wavefront-uniform
+  HalfAcc r;
+  if (live) {
     const int ti = T1 ? 0 : a.type[i];
-    const int32_t cnt = a.nnbr[i];
-    const int32_t *row = a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1));
-    const double L0 = a.b.L[0], L1 = a.b.L[1], L2 = a.b.L[2];
-    const double iL0 = a.b.invL[0], iL1 = a.b.invL[1], iL2 = a.b.invL[2];
-    // Neighboring lanes hold similar rows; starting each lane at a different
-    // slot spreads the simultaneous atomic updates over different atoms.
-    const int32_t rot = cnt > 0 ? (int32_t)((5u * (threadIdx.x & (kWave - 1))) % (uint32_t)cnt) : 0;
-    for (int32_t k = 0; k < cnt; ++k) {
-      int32_t kk = k + rot;
-      if (kk >= cnt) kk -= cnt;
-      const int32_t j = row[(int64_t)kk * kWave];
-      const double dx = min_image(xi - a.x[3 * (int64_t)j], L0, iL0);
-      const double dy = min_image(yi - a.x[3 * (int64_t)j + 1], L1, iL1);
-      const double dz = min_image(zi - a.x[3 * (int64_t)j + 2], L2, iL2);
-      const double r2 = dist2(dx, dy, dz);
-      if (r2 < a.rc2) {
-        Coef c;
-        if constexpr (T1) {
-          c = c1;
-        } else {
-          const double *t = tab + 4 * (ti * a.ntypes + a.type[j]);
-          c = Coef{t[0], t[1], t[2], t[3]};
-        }
-        const PairOut p = lj_pair<MIXED, EV>(dx, dy, dz, r2, c);
-        fx += p.fx;
-        fy += p.fy;
-        fz += p.fz;
-        unsafeAtomicAdd(&a.F[3 * (int64_t)j], -p.fx);
-        unsafeAtomicAdd(&a.F[3 * (int64_t)j + 1], -p.fy);
-        unsafeAtomicAdd(&a.F[3 * (int64_t)j + 2], -p.fz);
-        if constexpr (EV) {
-          e += p.u;
-          if (a.e_atom) unsafeAtomicAdd(&a.e_atom[j], 0.5 * p.u);
-          wxx = __builtin_fma(dx, p.fx, wxx);
-          wyy = __builtin_fma(dy, p.fy, wyy);
-          wzz = __builtin_fma(dz, p.fz, wzz);
-          wxy = __builtin_fma(dx, p.fy, wxy);
-          wxz = __builtin_fma(dx, p.fz, wxz);
-          wyz = __builtin_fma(dy, p.fz, wyz);
-        }
-      }
+    const int32_t ctot = a.nnbr[i];
+    const int32_t cnt = ctot > t ? (ctot - t + kHalfTeam - 1) / kHalfTeam : 0;
+    const int32_t *row =
+        a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
+    if (interior)
+      half_row<MIXED, T1, EV, EATOM, false, WIDE, U>(a, s, row, cnt, xi, yi, zi, ti, c1, tab, r);
+    else
+      half_row<MIXED, T1, EV, EATOM, true, WIDE, U>(a, s, row, cnt, xi, yi, zi, ti, c1, tab, r);
+  }
+  const double e_lane = r.e;
+#pragma unroll
+  for (int mask = kHalfTeam / 2; mask > 0; mask >>= 1) {
+    r.fx += __shfl_xor(r.fx, mask, kWave);
+    r.fy += __shfl_xor(r.fy, mask, kWave);
+    r.fz += __shfl_xor(r.fz, mask, kWave);
+    if constexpr (EATOM) r.e += __shfl_xor(r.e, mask, kWave);
+  }
+  if (live && t == 0) {  // the owner's side of its pairs joins the j-side sums of its tile
+    const int32_t sl = half_slot(s, i >> 6);
+    const int l = i & (kWave - 1);
+    if (sl >= 0) {
+      unsafeAtomicAdd(&s.acc[sl][0][l], r.fx);
+      unsafeAtomicAdd(&s.acc[sl][1][l], r.fy);
+      unsafeAtomicAdd(&s.acc[sl][2][l], r.fz);
+      if constexpr (EATOM) unsafeAtomicAdd(&s.acc[sl][NV - 1][l], 0.5 * r.e);
+    } else {
+      unsafeAtomicAdd(&a.F[3 * (int64_t)i], r.fx);
+      unsafeAtomicAdd(&a.F[3 * (int64_t)i + 1], r.fy);
+      unsafeAtomicAdd(&a.F[3 * (int64_t)i + 2], r.fz);
+      if constexpr (EATOM) unsafeAtomicAdd(&a.e_atom[i], 0.5 * r.e);
     }
-    unsafeAtomicAdd(&a.F[3 * (int64_t)i], fx);
-    unsafeAtomicAdd(&a.F[3 * (int64_t)i + 1], fy);
-    unsafeAtomicAdd(&a.F[3 * (int64_t)i + 2], fz);
-    if (EV && a.e_atom) unsafeAtomicAdd(&a.e_atom[i], 0.5 * e);
+  }
+  __syncthreads();
+  // flush: slot sl's F block is the 3*64 consecutive doubles of its tile; wave w
+  // adds rows (sl, q) = w, w + kWaves, ..., 64 consecutive doubles per row
+  const int nsl = s.count < SLOTS ? s.count : SLOTS;
+  constexpr int kRows = NV;  // F in three rows of 64 doubles (+ e_atom)
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  for (int q = (int)threadIdx.x / kWave; q < nsl * kRows; q += kWaves) {
+    const int sl = q / kRows, part = q % kRows;
+    const int64_t base = (int64_t)s.tile_of[sl] * kWave;
+    if (part < 3) {
+      const int e = part * kWave + lane;  // element of the tile's F block
+      const int atom = e / 3, comp = e % 3;
+      const double v = s.acc[sl][comp][atom];
+      if (base + atom < a.n && v != 0.0) unsafeAtomicAdd(&a.F[3 * base + e], v);
+    } else {
+      const double v = s.acc[sl][NV - 1][lane];
+      if (base + lane < a.n && v != 0.0) unsafeAtomicAdd(&a.e_atom[base + lane], v);
+    }
   }
   if constexpr (EV) {
-    const double v[7] = {e, wxx, wyy, wzz, wxy, wxz, wyz};
-    block_sum<kForceWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
+    const double v[7] = {e_lane, r.wxx, r.wyy, r.wzz, r.wxy, r.wxz, r.wyz};
+    block_sum<kWaves, 7>(v, red, a.partial + (int64_t)blockIdx.x * kEvStride);
   }
 }
 
@@ -623,11 +836,35 @@ constexpr int kUnroll = 8;
 constexpr int kTeam = 2;
 constexpr int kTeamUnroll = 6;
 
+// Half-list blocks: 256 home atoms (512 threads), 32 tile slots, 4 entries per group.
+constexpr int kHalfAtoms = 256;
+constexpr int kHalfSlots = 32;
+constexpr int kHalfUnroll = 4;
+
+unsigned half_blocks(int64_t n) {
+  const int64_t b = (n + kHalfAtoms - 1) / kHalfAtoms;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+template <bool MIXED, bool T1, bool EV, bool EATOM>
+void launch_half(const ForceArgs &a, hipStream_t st) {
+  constexpr int kThreads = kHalfAtoms * kHalfTeam;
+  if (a.n <= kNarrowAtoms)
+    k_force_half<MIXED, T1, EV, EATOM, false, kHalfAtoms, kHalfSlots, kHalfUnroll>
+        <<<half_blocks(a.n), kThreads, 0, st>>>(a);
+  else
+    k_force_half<MIXED, T1, EV, EATOM, true, kHalfAtoms, kHalfSlots, kHalfUnroll>
+        <<<half_blocks(a.n), kThreads, 0, st>>>(a);
+}
+
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
-  if (kind == LJMD_HALF)
-    k_force_half<MIXED, T1, EV><<<nblk, kForceThreads, 0, st>>>(a);
-  else if (a.n <= kNarrowAtoms)
+  if (kind == LJMD_HALF) {
+    if (a.e_atom)
+      launch_half<MIXED, T1, EV, true>(a, st);
+    else
+      launch_half<MIXED, T1, EV, false>(a, st);
+  } else if (a.n <= kNarrowAtoms)
     k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, false, kTeam>
         <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
   else
@@ -690,8 +927,8 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   } else if (ev) {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
   }
-  if (ev)
-    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
+  const unsigned rows = n == 0 ? 1 : (kind == LJMD_HALF ? half_blocks(n) : nblk);
+  if (ev) k_colsum<1024><<<1, 1024, 0, st>>>(rows, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces");
 }
 
@@ -770,6 +1007,106 @@ int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, c
   if (ev)
     k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_compute_forces_csr");
+}
+
+namespace {
+template <bool MIXED, bool T1, bool EV, int V>
+void launch_aosoa_one(const ForceArgs &a, unsigned nblk, hipStream_t st) {
+  k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, false, kTeam, V>
+      <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
+}
+
+template <bool MIXED, int V>
+void launch_aosoa_v(const ForceArgs &a, bool ev, unsigned nblk, hipStream_t st) {
+  const bool t1 = a.ntypes == 1;
+  if (t1 && ev) launch_aosoa_one<MIXED, true, true, V>(a, nblk, st);
+  else if (t1) launch_aosoa_one<MIXED, true, false, V>(a, nblk, st);
+  else if (ev) launch_aosoa_one<MIXED, false, true, V>(a, nblk, st);
+  else launch_aosoa_one<MIXED, false, false, V>(a, nblk, st);
+}
+
+template <bool MIXED>
+void launch_aosoa_prec(const ForceArgs &a, int vlen, bool ev, unsigned nblk, hipStream_t st) {
+  if (vlen == 0) launch_aosoa_v<MIXED, 0>(a, ev, nblk, st);
+  else if (vlen == 8) launch_aosoa_v<MIXED, 8>(a, ev, nblk, st);
+  else launch_aosoa_v<MIXED, 64>(a, ev, nblk, st);
+}
+
+// One thread per element: [n][3] <-> AoSoA(V).
+template <int V, bool TO_AOSOA>
+__global__ __launch_bounds__(256) void k_aosoa_convert(int64_t n, const double *__restrict__ src,
+                                                        double *__restrict__ dst) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= 3 * n) return;
+  const int64_t i = q / 3;
+  const int k = (int)(q - 3 * i);
+  if constexpr (TO_AOSOA)
+    dst[aos_index<V>(i, k, n)] = src[q];
+  else
+    dst[q] = src[aos_index<V>(i, k, n)];
+}
+
+template <int V>
+void launch_convert_v(int64_t n, int to_aosoa, const double *src, double *dst, hipStream_t st) {
+  const unsigned nb = (unsigned)((3 * n + 255) / 256);
+  if (to_aosoa)
+    k_aosoa_convert<V, true><<<nb, 256, 0, st>>>(n, src, dst);
+  else
+    k_aosoa_convert<V, false><<<nb, 256, 0, st>>>(n, src, dst);
+}
+}  // namespace
+
+// Full-list forces over AoSoA(vlen) positions and forces (vlen 0: SoA; 1: the
+// [n][3] arrays of launch_forces; 8 or 64).  Same traversal and summation order
+// as the full-list kernel, so the same bits in any layout.
+int launch_forces_aosoa(const BoxK &b, int precision, double rc, int32_t ntypes, const double *eps,
+                        const double *sig, int64_t n, int vlen, const double *x,
+                        const int32_t *type, const int32_t *nbr, const int32_t *nnbr,
+                        int32_t maxn, double *F, double *e_atom, double *ev, void *ws,
+                        hipStream_t st) {
+  if (vlen == 1)
+    return launch_forces(b, precision, LJMD_FULL, rc, ntypes, eps, sig, n, x, type, nbr, nnbr,
+                         maxn, F, e_atom, ev, ws, st);
+  ForceArgs a{};
+  a.b = b;
+  a.rc = rc;
+  a.rc2 = rc * rc;
+  a.ntypes = ntypes;
+  a.eps = eps;
+  a.sig = sig;
+  a.n = (int32_t)n;
+  a.x = x;
+  a.type = type;
+  a.nbr = nbr;
+  a.nnbr = nnbr;
+  a.maxn = maxn;
+  a.F = F;
+  a.e_atom = e_atom;
+  a.partial = (double *)ws;
+  const unsigned nblk = force_blocks(n);
+  const bool want_ev = ev != nullptr || e_atom != nullptr;
+  if (n > 0) {
+    if (precision == LJMD_MIXED)
+      launch_aosoa_prec<true>(a, vlen, want_ev, nblk, st);
+    else
+      launch_aosoa_prec<false>(a, vlen, want_ev, nblk, st);
+  } else if (ev) {
+    k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
+  }
+  if (ev)
+    k_colsum<1024><<<1, 1024, 0, st>>>(n > 0 ? nblk : 1, kEvStride, 7, a.partial, ev, 1.0, 0);
+  return check_launch("ljmd_compute_forces_aosoa");
+}
+
+int launch_aosoa_convert(int64_t n, int vlen, int to_aosoa, const double *src, double *dst,
+                         hipStream_t st) {
+  if (n > 0) {
+    if (vlen == 0) launch_convert_v<0>(n, to_aosoa, src, dst, st);
+    else if (vlen == 1) launch_convert_v<1>(n, to_aosoa, src, dst, st);
+    else if (vlen == 8) launch_convert_v<8>(n, to_aosoa, src, dst, st);
+    else launch_convert_v<64>(n, to_aosoa, src, dst, st);
+  }
+  return check_launch("ljmd_aosoa_convert");
 }
 
 // partial: this step's partial rows; ev: their sums, or NULL to leave them in

@@ -32,6 +32,21 @@ constexpr int kFlushRows = kWave / kBatch;  // list rows of a batch written per 
 
 __global__ void k_fill_scalar(int32_t *p, int32_t val) { *p = val; }
 
+// What a build pass writes: the tiled list (rows cut at maxn, counts in nnbr),
+// only the true row lengths (into nnbr), or compressed rows at csr[offsets[i]..]
+// (entries at or beyond cap dropped).
+enum BuildMode { kTiled = 0, kCount = 1, kCsr = 2 };
+
+// Output of a build pass.
+struct BuildOut {
+  int32_t *nbr;            // tiled list (kTiled)
+  int32_t *nnbr;           // row lengths (kTiled: cut at maxn; kCount: true)
+  int32_t maxn;
+  const int64_t *offsets;  // kCsr: row starts
+  int32_t *csr;            // kCsr: rows
+  int64_t cap;             // kCsr: capacity of csr
+};
+
 // Stencil of cell c: its candidate ranges [rs[s], rs[s] + len) in sorted order
 // and the prefix pre[s] of their lengths.  Returns the number of ranges.
 __device__ __forceinline__ int stencil_ranges(const GridK &g, int32_t c, const int32_t *cell_start,
@@ -102,12 +117,16 @@ __device__ __forceinline__ int32_t locate(int32_t t, const int32_t *rs, const in
 
 // Register-staged build of one cell's rows (candidates <= SLOTS * 64).  BUF:
 // rows are compacted in LDS (maxn <= ROWCAP) rather than stored directly.
-template <bool HALF, bool WRAP, bool BUF, int SLOTS, int ROWCAP>
+template <bool HALF, bool WRAP, bool BUF, int SLOTS, int ROWCAP, int MODE>
 __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const double *__restrict__ x,
                                              int32_t h0, int32_t h1, int32_t total, int nslot,
-                                             const int32_t *rs, const int32_t *pre, int32_t maxn,
-                                             int32_t *__restrict__ nbr, int32_t *__restrict__ nnbr,
-                                             int32_t *rowbuf, int32_t *rowcnt, int32_t &maxc) {
+                                             const int32_t *rs, const int32_t *pre,
+                                             const BuildOut &o, int32_t *rowbuf, int32_t *rowcnt,
+                                             int32_t &maxc) {
+  const int32_t maxn = o.maxn;
+  int32_t *__restrict__ nbr = o.nbr;
+  int32_t *__restrict__ nnbr = o.nnbr;
+  static_assert(!BUF || MODE == kTiled, "rows are buffered only for the tiled list");
   const int lane = threadIdx.x & (kWave - 1);
   const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
   const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
@@ -150,7 +169,9 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
       const int src = (b0 - h0) % kWave + bi;
       const double xi = readlane_f64(hx, src), yi = readlane_f64(hy, src),
                    zi = readlane_f64(hz, src);
-      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      int32_t *row = MODE == kTiled ? nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1))
+                                    : nullptr;
+      const int64_t off = MODE == kCsr ? o.offsets[i] : 0;
       int32_t base = 0;
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
@@ -164,11 +185,13 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
           const double r2 = dist2(dx, dy, dz);
           const bool ok = qj[r] >= 0 && r2 < rl2 && (HALF ? qj[r] > i : qj[r] != i);
           const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
-          if (ok) {
+          if (MODE != kCount && ok) {
             const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
                                          (uint32_t)(m >> 32),
                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (k < maxn) {
+            if constexpr (MODE == kCsr) {
+              if (off + k < o.cap) o.csr[off + k] = qj[r];
+            } else if (k < maxn) {
               if (buffered)
                 rowbuf[bi * kRowStride + k] = qj[r];
               else
@@ -178,11 +201,11 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
           base += (int32_t)__popcll(m);
         }
       }
-      if (lane == 0) rowcnt[bi] = base < maxn ? base : maxn;
+      if (lane == 0) rowcnt[bi] = MODE == kTiled ? (base < maxn ? base : maxn) : base;
       maxc = base > maxc ? base : maxc;
     }
     __syncthreads();  // rowbuf / rowcnt written by other lanes of this one-wavefront block
-    if (lane < nb) nnbr[b0 + lane] = rowcnt[lane];
+    if (MODE != kCsr && lane < nb) nnbr[b0 + lane] = rowcnt[lane];
     if (buffered) {
       // lane (a, h) = (lane % kBatch, lane / kBatch) stores rows k = h, h + kFlushRows,
       // ... of batch atom a: every store instruction covers kFlushRows list rows of
@@ -199,13 +222,12 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   }
 }
 
-template <bool HALF, int SLOTS, int ROWCAP>
+template <bool HALF, int SLOTS, int ROWCAP, int MODE = kTiled>
 __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
                                                  const double *__restrict__ x,
                                                  const int32_t *__restrict__ cell_start,
-                                                 int32_t maxn, int32_t *__restrict__ nbr,
-                                                 int32_t *__restrict__ nnbr,
-                                                 int32_t *__restrict__ max_count) {
+                                                 BuildOut o, int32_t *__restrict__ max_count) {
+  const int32_t maxn = o.maxn;
   __shared__ int32_t rs[27];
   __shared__ int32_t pre[28];
   __shared__ int32_t rowbuf[kBatch * (ROWCAP + 1)];
@@ -230,11 +252,15 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
       wrap |= g.nc[k] < 4 || cc[k] == 0 || cc[k] == g.nc[k] - 1;
   }
   if (nslot <= SLOTS) {
-#define LJMD_STAGED(W, B)                                                                  \
-  build_staged<HALF, W, B, SLOTS, ROWCAP>(b, rl2, x, h0, h1, total, nslot, rs, pre, maxn, nbr, \
-                                          nnbr, rowbuf, rowcnt, maxc)
-    if (maxn <= ROWCAP) {
-      if (wrap) LJMD_STAGED(true, true); else LJMD_STAGED(false, true);
+#define LJMD_STAGED(W, B)                                                                     \
+  build_staged<HALF, W, B, SLOTS, ROWCAP, MODE>(b, rl2, x, h0, h1, total, nslot, rs, pre, o, \
+                                                rowbuf, rowcnt, maxc)
+    if constexpr (MODE == kTiled) {
+      if (maxn <= ROWCAP) {
+        if (wrap) LJMD_STAGED(true, true); else LJMD_STAGED(false, true);
+      } else {
+        if (wrap) LJMD_STAGED(true, false); else LJMD_STAGED(false, false);
+      }
     } else {
       if (wrap) LJMD_STAGED(true, false); else LJMD_STAGED(false, false);
     }
@@ -244,7 +270,10 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
     const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
     for (int32_t i = h0; i < h1; ++i) {
       const double xi = x[3 * (int64_t)i], yi = x[3 * (int64_t)i + 1], zi = x[3 * (int64_t)i + 2];
-      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      int32_t *row = MODE == kTiled
+                         ? o.nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1))
+                         : nullptr;
+      const int64_t off = MODE == kCsr ? o.offsets[i] : 0;
       int32_t base = 0;
       for (int r = 0; r < nslot; ++r) {
         const int32_t t = r * kWave + lane;
@@ -258,45 +287,91 @@ __global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
           ok = dist2(dx, dy, dz) < rl2 && (HALF ? j > i : j != i);
         }
         const uint64_t m = __ballot(ok);
-        if (ok) {
+        if (MODE != kCount && ok) {
           const int32_t k = base + (int32_t)__builtin_amdgcn_mbcnt_hi(
                                        (uint32_t)(m >> 32),
                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (k < maxn) row[(int64_t)k * kWave] = j;
+          if constexpr (MODE == kCsr) {
+            if (off + k < o.cap) o.csr[off + k] = j;
+          } else if (k < maxn) {
+            row[(int64_t)k * kWave] = j;
+          }
         }
         base += (int32_t)__popcll(m);
       }
-      if (lane == 0) nnbr[i] = base < maxn ? base : maxn;
+      if (MODE != kCsr && lane == 0) o.nnbr[i] = MODE == kTiled ? (base < maxn ? base : maxn) : base;
       maxc = base > maxc ? base : maxc;
     }
   }
-  if (lane == 0) atomicMax(max_count, maxc);
+  if (lane == 0 && max_count) atomicMax(max_count, maxc);
+}
+
+template <int MODE>
+void launch_mode(const GridK &g, const BoxK &b, double rl2, bool half, const double *x,
+                 const int32_t *cell_start, const BuildOut &o, int32_t *max_count,
+                 hipStream_t st) {
+  if (MODE != kTiled || o.maxn <= kRowCap) {
+    if (half)
+      k_build<true, kSlots, kRowCap, MODE><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, o,
+                                                                      max_count);
+    else
+      k_build<false, kSlots, kRowCap, MODE><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start,
+                                                                       o, max_count);
+  } else {
+    if (half)
+      k_build<true, kDenseSlots, kDenseRowCap, MODE><<<g.ncells, kWave, 0, st>>>(
+          g, b, rl2, x, cell_start, o, max_count);
+    else
+      k_build<false, kDenseSlots, kDenseRowCap, MODE><<<g.ncells, kWave, 0, st>>>(
+          g, b, rl2, x, cell_start, o, max_count);
+  }
 }
 
 }  // namespace
+
+int launch_offsets(int64_t n, const int32_t *counts, int64_t *offsets, void *ws, hipStream_t st);
+size_t csr_workspace(int64_t n);
+
+// Compressed rows straight from the cells: a counting pass (true row lengths),
+// their exclusive scan into offsets (offsets[n] = total), then a filling pass
+// that writes row i at csr[offsets[i] ..] (entries at or beyond cap dropped:
+// the caller compares offsets[n] with cap and builds again with more room).
+size_t build_csr_workspace(int64_t n) {
+  return (((size_t)(n > 0 ? n : 1) * sizeof(int32_t) + 255) / 256) * 256 + csr_workspace(n);
+}
+
+int launch_build_csr(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n,
+                     const double *x, const int32_t *cell_start, int64_t *offsets, int32_t *csr,
+                     int64_t cap, void *ws, hipStream_t st) {
+  int32_t *counts = (int32_t *)ws;
+  void *scan_ws = (char *)ws + (((size_t)(n > 0 ? n : 1) * sizeof(int32_t) + 255) / 256) * 256;
+  const double rl2 = rlist * rlist;
+  const bool half = kind == LJMD_HALF;
+  BuildOut o{};
+  o.nnbr = counts;
+  o.maxn = 1;
+  if (n > 0) launch_mode<kCount>(g, b, rl2, half, x, cell_start, o, nullptr, st);
+  const int rc = launch_offsets(n, counts, offsets, scan_ws, st);
+  if (rc != LJMD_OK) return rc;
+  if (n > 0) {
+    o.offsets = offsets;
+    o.csr = csr;
+    o.cap = cap;
+    launch_mode<kCsr>(g, b, rl2, half, x, cell_start, o, nullptr, st);
+  }
+  return check_launch("ljmd_build_neighbors_csr");
+}
 
 int launch_build(const GridK &g, const BoxK &b, double rlist, int kind, int64_t n, const double *x,
                  const int32_t *cell_start, int32_t maxn, int32_t *nbr, int32_t *nnbr,
                  int32_t *max_count, hipStream_t st) {
   k_fill_scalar<<<1, 1, 0, st>>>(max_count, 0);
   if (n > 0) {
-    const double rl2 = rlist * rlist;
-    const bool half = kind == LJMD_HALF;
-    if (maxn <= kRowCap) {
-      if (half)
-        k_build<true, kSlots, kRowCap><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start, maxn,
-                                                                  nbr, nnbr, max_count);
-      else
-        k_build<false, kSlots, kRowCap><<<g.ncells, kWave, 0, st>>>(g, b, rl2, x, cell_start,
-                                                                   maxn, nbr, nnbr, max_count);
-    } else {
-      if (half)
-        k_build<true, kDenseSlots, kDenseRowCap><<<g.ncells, kWave, 0, st>>>(
-            g, b, rl2, x, cell_start, maxn, nbr, nnbr, max_count);
-      else
-        k_build<false, kDenseSlots, kDenseRowCap><<<g.ncells, kWave, 0, st>>>(
-            g, b, rl2, x, cell_start, maxn, nbr, nnbr, max_count);
-    }
+    BuildOut o{};
+    o.nbr = nbr;
+    o.nnbr = nnbr;
+    o.maxn = maxn;
+    launch_mode<kTiled>(g, b, rlist * rlist, kind == LJMD_HALF, x, cell_start, o, max_count, st);
   }
   return check_launch("ljmd_build_neighbors");
 }

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (EBOX, EHIP, EINVAL, EWORKSPACE, FP64, FULL, HALF, KICK, KICK_DRIFT,  # noqa: F401
                    KICK_KICK_DRIFT, KINETIC,
                    MAX_TEAM, MAX_TYPES, MIXED, OP_BACKWARD, OP_BIN, OP_CSR, OP_FORCES,
-                   OP_DISPLACEMENT, OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE, OP_LOSS, OP_MD_CHAIN,
+                   OP_BUILD_CSR, OP_DISPLACEMENT, OP_EWALD_REAL, OP_FORCES_CSR, OP_INTEGRATE,
+                   OP_LOSS, OP_MD_CHAIN,
                    OP_SPH, OP_SPME,
                    SPME_MAX_GRID, TILE, LjmdError, make_box)
 
@@ -152,6 +153,39 @@ def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn
     return F, e_atom, ev
 
 
+def build_neighbors_csr(L, rlist, kind, x, cell_start, cap=None, offsets=None, csr=None, ws=None):
+    """Compressed (CSR) Verlet list straight from the cells: (offsets int64 [n+1],
+    csr int32).  With cap None the capacity starts from the mean density and the
+    list is built again, once, if the total read back exceeds it (a sync)."""
+    n = x.shape[0]
+    dev = x.device
+    _need(x, "x", torch.float64, (n, 3))
+    _need(cell_start, "cell_start", torch.int32, None, dev)
+    if offsets is None:
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    _need(offsets, "offsets", torch.int64, (n + 1,), dev)
+    ws, need = _ws(OP_BUILD_CSR, n, dev, ws=ws)
+    b = make_box(L)
+    guess = cap is None
+    if guess:
+        vol = float(L[0]) * float(L[1]) * float(L[2])
+        mean = 4.0 / 3.0 * 3.141592653589793 * rlist ** 3 * n / vol
+        cap = int((mean * (0.5 if kind == HALF else 1.0) * 1.1 + 8) * n) + 64
+    while True:
+        if csr is None or csr.numel() < cap:
+            csr = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        _need(csr, "csr", torch.int32, None, dev)
+        _lib.check(_lib.load().ljmd_build_neighbors_csr(
+            ctypes.byref(b), float(rlist), int(kind), n, _ptr(x), _ptr(cell_start), _ptr(offsets),
+            _ptr(csr), int(csr.numel()), _ptr(ws), need, _stream(dev)), "ljmd_build_neighbors_csr")
+        if not guess:
+            return offsets, csr
+        total = int(offsets[n].item())
+        if total <= csr.numel():
+            return offsets, csr
+        cap, csr = total, None
+
+
 def list_to_csr(nbr, nnbr, maxn, cap=None, offsets=None, csr=None, ws=None):
     """(offsets int64 [n+1], csr int32 [cap]) = compressed copy of a tiled list.  With
     cap None the capacity is the exact total, read back from the device (a sync)."""
@@ -206,6 +240,57 @@ def compute_forces_csr(L, precision, rc, eps, sigma, x, types, offsets, csr, tea
         ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, _ptr(x),
         _ptr(types), _ptr(offsets), _ptr(csr), int(team), _ptr(F), _ptr(e_atom), _ptr(ev),
         _ptr(ws), need, _stream(dev)), "ljmd_compute_forces_csr")
+    return F, e_atom, ev
+
+
+AOSOA_VLENS = (0, 1, 8, 64)  # 0: plain SoA; 1: [n][3]
+
+
+def aosoa_convert(src, vlen, to_aosoa, n=None, dst=None):
+    """[n][3] rows -> flat AoSoA(vlen) array of 3n (to_aosoa) or back."""
+    dev = src.device
+    if n is None:
+        n = src.shape[0] if to_aosoa else src.numel() // 3
+    _need(src, "src", torch.float64, (n, 3) if to_aosoa else (3 * n,))
+    if dst is None:
+        dst = torch.empty(3 * n, dtype=torch.float64, device=dev) if to_aosoa else \
+            torch.empty(n, 3, dtype=torch.float64, device=dev)
+    _need(dst, "dst", torch.float64, (3 * n,) if to_aosoa else (n, 3), dev)
+    _lib.check(_lib.load().ljmd_aosoa_convert(n, int(vlen), 1 if to_aosoa else 0, _ptr(src),
+                                              _ptr(dst), _stream(dev)), "ljmd_aosoa_convert")
+    return dst
+
+
+def compute_forces_aosoa(L, precision, rc, eps, sigma, x, types, nbr, nnbr, maxn, vlen, F=None,
+                         e_atom=None, ev=None, want_energy=True, ws=None):
+    """FULL-list forces with positions x and forces F flat [3n] in AoSoA(vlen) layout."""
+    n = types.shape[0]
+    dev = x.device
+    ntypes = _ntypes(eps)
+    _need(x, "x", torch.float64, (3 * n,))
+    _need(eps, "eps", torch.float64, None, dev)
+    _need(sigma, "sigma", torch.float64, tuple(eps.shape), dev)
+    _need(types, "types", torch.int32, (n,), dev)
+    _need(nbr, "nbr", torch.int32, None, dev)
+    _need(nnbr, "nnbr", torch.int32, (n,), dev)
+    if nbr.numel() < list_shape(n, maxn)[0]:
+        raise ValueError("nbr is smaller than the tiled list of n rows x maxn")
+    if F is None:
+        F = torch.empty_like(x)
+    if want_energy:
+        if e_atom is None:
+            e_atom = torch.empty(n, dtype=torch.float64, device=dev)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=dev)
+    _need(F, "F", torch.float64, (3 * n,), dev)
+    _need(e_atom, "e_atom", torch.float64, (n,), dev)
+    _need(ev, "ev", torch.float64, (7,), dev)
+    ws, need = _ws(OP_FORCES, n, dev, ws=ws)
+    b = make_box(L)
+    _lib.check(_lib.load().ljmd_compute_forces_aosoa(
+        ctypes.byref(b), int(precision), float(rc), ntypes, _ptr(eps), _ptr(sigma), n, int(vlen),
+        _ptr(x), _ptr(types), _ptr(nbr), _ptr(nnbr), int(maxn), _ptr(F), _ptr(e_atom), _ptr(ev),
+        _ptr(ws), need, _stream(dev)), "ljmd_compute_forces_aosoa")
     return F, e_atom, ev
 
 

@@ -140,3 +140,86 @@ def test_csr_team2_bitwise_tiled_and_teams_deterministic(dev, prec):
         Fn, _, _ = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types,
                                           off, csr, team=team, want_energy=False)
         assert torch.equal(Fn, a[0]), team
+
+
+# ------------------------------------------------------------- AoSoA layouts --
+
+@pytest.mark.parametrize("vlen", [0, 1, 8, 64])
+@pytest.mark.parametrize("name", ["gas1000", "lj256", "lj32k", "lj32k_fm"])
+def test_aosoa_forces_bitwise_equal_and_vs_oracle(dev, orc, name, vlen):
+    """Positions and forces in AoSoA(vlen) (0: SoA): forces, per-atom energies, energy and
+    virial bitwise those of the [n][3] kernel (same traversal and order) for FP64 and
+    mixed, and the FP64 forces against the oracle; the conversion round-trips exactly."""
+    import torch
+    from paper_2109_09056_amd import ops
+    sim = _sim(dev, name)
+    nl = sim.nl
+    xa = ops.aosoa_convert(sim.x, vlen, True)
+    assert torch.equal(ops.aosoa_convert(xa, vlen, False, n=sim.n), sim.x)
+    if vlen not in (0, 1):  # chunk-major; the last chunk holds the remaining atoms
+        for i in (0, vlen + 3, sim.n - 1):
+            c = i // vlen
+            wid = min(vlen, sim.n - c * vlen)
+            base = c * 3 * vlen + i - c * vlen
+            assert float(xa[base + wid].item()) == float(sim.x[i, 1].item())
+            assert float(xa[base + 2 * wid].item()) == float(sim.x[i, 2].item())
+    for prec in (ops.FP64, ops.MIXED):
+        F, e, ev = ops.compute_forces(sim.L, prec, ops.FULL, 2.5, sim.eps, sim.sigma, sim.x,
+                                      sim.types, nl.nbr, nl.nnbr, nl.maxn)
+        Fa, ea, eva = ops.compute_forces_aosoa(sim.L, prec, 2.5, sim.eps, sim.sigma, xa,
+                                               sim.types, nl.nbr, nl.nnbr, nl.maxn, vlen)
+        assert torch.equal(ops.aosoa_convert(Fa, vlen, False, n=sim.n), F)
+        assert torch.equal(ea, e) and torch.equal(eva, ev)
+        if prec == ops.FP64:
+            Fo = _oracle(orc, name)[0]
+            Fg = ops.scatter_rows(sim.ids, ops.aosoa_convert(Fa, vlen, False, n=sim.n))
+            assert max_rel_vec(Fg.cpu().numpy(), Fo) <= 1e-12
+
+
+def test_aosoa_rejects_other_vector_lengths(dev):
+    import torch
+    from paper_2109_09056_amd import _lib, ops
+    x = torch.zeros(10, 3, dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.LjmdError):
+        ops.aosoa_convert(x, 16, True)
+
+
+# ------------------------------------------------- compressed rows from the cells --
+
+@pytest.mark.parametrize("kind", ["full", "half"])
+@pytest.mark.parametrize("name", ["lj256", "gas1000", "lj32k", "lj32k_fm"])
+def test_direct_csr_build_equals_tiled_rows(dev, name, kind):
+    """Rows built straight into CSR equal the tiled build's rows entry by entry (same order),
+    full and half; a capacity below the total keeps the offsets and drops only the tail."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    sim = _sim(dev, name)
+    K = ops.FULL if kind == "full" else ops.HALF
+    nl = md.NeighborList(sim.L, sim.rlist, K, device=dev).build(sim.x, sim.cell_start)
+    off, csr = ops.build_neighbors_csr(sim.L, sim.rlist, K, sim.x, sim.cell_start)
+    rows = decode_rows(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn)
+    assert int(nl.max_count.item()) <= nl.maxn
+    off_h, csr_h = off.cpu().numpy(), csr.cpu().numpy()
+    cnt = np.array([r.size for r in rows])
+    assert np.array_equal(np.diff(off_h), cnt) and off_h[0] == 0
+    assert np.array_equal(csr_h[:off_h[-1]], np.concatenate(rows))
+    cap = int(off_h[-1]) // 2
+    small = torch.full((cap,), -7, dtype=torch.int32, device=dev)
+    off2, _ = ops.build_neighbors_csr(sim.L, sim.rlist, K, sim.x, sim.cell_start, cap=cap,
+                                      csr=small)
+    assert torch.equal(off2, off) and np.array_equal(small.cpu().numpy(), csr_h[:cap])
+
+
+def test_direct_csr_forces_vs_oracle(dev, orc):
+    """Team traversal over the direct CSR list: the oracle's forces and energies."""
+    from paper_2109_09056_amd import ops
+    name = "lj32k_fm"
+    sim = _sim(dev, name)
+    off, csr = ops.build_neighbors_csr(sim.L, sim.rlist, ops.FULL, sim.x, sim.cell_start)
+    Fo, eo, _, _ = _oracle(orc, name)
+    for team in (1, 4):
+        F, e, _ = ops.compute_forces_csr(sim.L, ops.FP64, 2.5, sim.eps, sim.sigma, sim.x,
+                                         sim.types, off, csr, team=team)
+        assert max_rel_vec(ops.scatter_rows(sim.ids, F).cpu().numpy(), Fo) <= 1e-12
+        eg = ops.scatter_rows(sim.ids, e.reshape(-1, 1)).cpu().numpy().reshape(-1)
+        assert np.abs(eg - eo).max() <= 1e-12 * np.abs(eo).max()

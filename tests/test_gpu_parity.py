@@ -282,6 +282,48 @@ def test_forces_mixed(dev, oracle_forces_cache, name, kind):
     assert abs(ev[0] - eo.sum()) <= 1e-6 * abs(eo.sum())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_half_forces_in_scrambled_order(dev, orc, oracle_forces_cache, prec):
+    """The half-list kernel on the 32k liquid with its atoms (and list indices) put in a
+    random order: every block then touches far more 64-atom tiles than it keeps j-side
+    sums for, so most pairs take the direct-atomic path.  Forces, energies and virial
+    against the oracle."""
+    import torch
+    from helpers import list_pairs
+    from paper_2109_09056_amd import ops
+    x, L, _, eps, sig, (Fo, eo, Wo, _) = oracle_forces_cache("lj32k")
+    n = x.shape[0]
+    nl, ids, xs = gpu_lists(dev, x, L, 2.8, ops.HALF)
+    i, j = list_pairs(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn)
+    perm = np.random.default_rng(3).permutation(n)  # sorted position k -> new position perm[k]
+    ni, nj = perm[i], perm[j]
+    order = np.argsort(ni, kind="stable")
+    ni, nj = ni[order], nj[order]
+    cnt = np.bincount(ni, minlength=n)
+    maxn = int(cnt.max())
+    tiles = (n + 63) // 64
+    nbr = np.zeros((tiles, maxn, 64), dtype=np.int32)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    k = np.arange(ni.size) - start[ni]
+    nbr[ni // 64, k, ni % 64] = nj
+    x_new = np.empty((n, 3))
+    x_new[perm] = xs.cpu().numpy()
+    ids_new = np.empty(n, dtype=np.int64)
+    ids_new[perm] = ids.cpu().numpy()
+    P = ops.FP64 if prec == "fp64" else ops.MIXED
+    one = T([1.0], dev, torch.float64)
+    F, e, ev = ops.compute_forces(L, P, ops.HALF, 2.5, one, one, T(x_new, dev),
+                                  torch.zeros(n, dtype=torch.int32, device=dev),
+                                  T(nbr.reshape(-1), dev), T(cnt.astype(np.int32), dev), maxn)
+    Fg, eg = np.empty((n, 3)), np.empty(n)
+    Fg[ids_new] = F.cpu().numpy()
+    eg[ids_new] = e.cpu().numpy()
+    if P == ops.FP64:
+        check_fp64(Fg, eg, ev.cpu().numpy(), Fo, eo, Wo)
+    else:
+        check_mixed(Fg, eg, Fo, eo)
+
+
 def test_forces_full_list_bitwise_deterministic(dev):
     import torch
     from paper_2109_09056_amd import ops
