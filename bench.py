@@ -28,11 +28,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Counter figures of the fused step kernel k_force_full<mixed, one type, EV, 6, interior,
-# step, narrow, team 2> on the 500,000-atom workload, from the rocprofv3 summaries committed in
-# profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
+# step, narrow, team 2, [n][3]> on the 500,000-atom workload, from the rocprofv3 summaries
+# committed in profiles/ (k_force_full_step_lj500k_hbm_counters.txt, ..._pipeline_counters.txt):
 # HBM bytes per dispatch = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the scales a 512 MiB copy
 # gives the two counters); set to None whenever the kernel changes until re-measured.
-FORCE_TRAFFIC = 232.89e6
+FORCE_COUNTERS_FROM = ("profiles/k_force_full_step_lj500k_hbm_counters.txt and "
+                       "..._pipeline_counters.txt (rocprofv3 --pmc on this kernel build)")
+FORCE_TRAFFIC = 234.54e6
 FORCE_VALU_BUSY = 0.542
 FORCE_TA_BUSY = 0.769
 
@@ -58,6 +60,9 @@ def parse():
                     help="run only the SPME leg (500,000 charges) and print its JSON object")
     ap.add_argument("--charged-only", action="store_true",
                     help="run only the charged LJ + SPME MD leg and print its JSON object")
+    ap.add_argument("--half-only", action="store_true",
+                    help="run only the half-list force calls (32,000 and 500,000 atoms) beside the "
+                         "full-list ones and print their JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (x5), to calibrate HBM "
                          "byte counters")
@@ -225,6 +230,37 @@ def config1_matrix(dev, steps=1000, warmup=50):
                 "mean_list_length": round(float(sim.nl.nnbr.double().mean().item()), 3)}
             del sim
     out["natoms"], out["steps"], out["unit"] = w.natoms, steps, "atom-steps/s"
+    return out
+
+
+def half_bench(dev, reps=20):
+    """Force calls on the 32,000- and 500,000-atom starts (mixed): the half list (each pair
+    once, partner sums through LDS tiles and FP64 atomics) against the full list, with
+    per-atom energies and virial and forces only, HIP events around `reps` calls each."""
+    import torch
+    import lj_inputs as li
+    from paper_2109_09056_amd import md, ops
+    out = {}
+    for name in ("lj32k", "lj500k"):
+        w = li.WORKLOADS[name]
+        s = li.make_system(w)
+        sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, device=dev)
+        sim.load(s["x"], s["v"])
+        hl = md.NeighborList(sim.L, sim.rlist, ops.HALF, device=dev).build(sim.x, sim.cell_start)
+        F, e = torch.empty_like(sim.F), torch.empty_like(sim.e_atom)
+        ev = torch.empty(7, dtype=torch.float64, device=dev)
+        row = {}
+        for lname, nl, kind in (("full", sim.nl, ops.FULL), ("half", hl, ops.HALF)):
+            for ename, want in (("energies", True), ("forces_only", False)):
+                row[f"{lname}_{ename}_us"] = round(event_time(lambda: ops.compute_forces(
+                    w.box, ops.MIXED, kind, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
+                    nl.nnbr, nl.maxn, F=F, e_atom=e if want else None, ev=ev if want else None,
+                    want_energy=want, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+        row["half_over_full_energies"] = round(row["half_energies_us"] / row["full_energies_us"], 3)
+        row["half_over_full_forces_only"] = round(row["half_forces_only_us"] /
+                                                  row["full_forces_only_us"], 3)
+        out[name] = row
+        del sim, hl
     return out
 
 
@@ -578,6 +614,9 @@ def main():
     if args.spme_only:
         print(json.dumps({"spme_500k": spme_bench(dev)}), flush=True)
         return
+    if args.half_only:
+        print(json.dumps({"half_list": half_bench(dev)}), flush=True)
+        return
     if args.charged_only:
         print(json.dumps({"charged_md_500k": charged_md_bench(dev)}), flush=True)
         return
@@ -617,6 +656,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(FORCE_TRAFFIC) if FORCE_TRAFFIC else None,
                      "valu_busy": FORCE_VALU_BUSY, "texture_addr_busy": FORCE_TA_BUSY,
+                     "counters_from": FORCE_COUNTERS_FROM,
                      "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
     }
     checked, dangerous, dmax = sim.displacement_report()

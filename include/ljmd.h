@@ -19,6 +19,9 @@
  *   ljmd_md_step_chained, ljmd_md_step_sums
  *                         the same step with its energy sums formed during the
  *                         next step's launch (one launch per step)
+ *   ljmd_md_step_noalloc  the fused step for callers that cannot allocate
+ *   ljmd_max_displacement largest displacement since a list was built (the
+ *                         dangerous-build check of a fixed rebuild cadence)
  *   ljmd_build_neighbors_csr, ljmd_list_to_csr, ljmd_compute_forces_csr
  *                         compressed list form and team-per-atom traversal
  *   ljmd_compute_forces_aosoa, ljmd_aosoa_convert
