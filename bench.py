@@ -81,13 +81,33 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 5}), flush=True)
 
 
-EVENT_EVERY = 10
+EVENT_SPAN = 10
 WINDOWS = 3
+
+
+def span_events(first_step, steps, rebuild_every):
+    """Per-step items for LJSim.step's force_events: one event pair spanning the launches
+    of EVENT_SPAN consecutive steps with no rebuild between them (a rebuild runs before its
+    step's start event), so the average launch is the pair's time / EVENT_SPAN and the
+    timed window carries two event records; with no such run, every launch alone.
+    Returns (items, [(start, end, launches)])."""
+    import torch
+    new = lambda: torch.cuda.Event(enable_timing=True)
+    rebuild = [(first_step + k) % rebuild_every == 0 for k in range(steps)]
+    span = min(EVENT_SPAN, steps)
+    for k0 in range(steps - span + 1):
+        if span > 1 and not any(rebuild[k0 + 1:k0 + span]):
+            a, b = new(), new()
+            items = [None] * steps
+            items[k0], items[k0 + span - 1] = (a, None), (None, b)
+            return items, [(a, b, span)]
+    items = [(new(), new()) for _ in range(steps)]
+    return items, [(a, b, 1) for a, b in items]
 
 
 def md_run(w, s, precision, steps, warmup, dev, windows=WINDOWS, kind=None):
     """Time `windows` consecutive windows of `steps` MD steps each after `warmup` steps;
-    returns (median window seconds, all window seconds, force-call ms list, sim).
+    returns (median window seconds, all window seconds, per-launch force-call ms list, sim).
 
     Python's garbage collector is run before and held off during the windows: a full
     collection of this process's objects costs tens of milliseconds, which would land
@@ -99,29 +119,32 @@ def md_run(w, s, precision, steps, warmup, dev, windows=WINDOWS, kind=None):
                    kind=ops.FULL if kind is None else kind, dt=w.dt,
                    rebuild_every=w.rebuild_every, device=dev)
     sim.load(s["x"], s["v"])
-    sim.step(warmup)
-    times, force_ms = [], []
-    for _ in range(windows):
-        # events around every EVENT_EVERY-th force launch: each recorded event costs the
-        # stream a few microseconds, so timing every launch would slow the loop itself
-        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  if k % EVENT_EVERY == EVENT_EVERY // 2 else None for k in range(steps)]
-        for e in events:  # HIP events are created at their first record: do it here
-            if e is not None:
-                e[0].record()
-                e[1].record()
-        gc.collect()
-        gc.disable()
-        try:
-            torch.cuda.synchronize()
+    # every window's timing events, created (at their first record) before anything is timed
+    plan = []
+    for k in range(windows):
+        events, pairs = span_events(sim.step_count + warmup + k * steps + 1, steps,
+                                    w.rebuild_every)
+        for a, b, _ in pairs:
+            a.record()
+            b.record()
+        plan.append((events, pairs))
+    times = []
+    gc.collect()
+    gc.disable()
+    try:
+        sim.step(warmup)
+        # windows back to back: only the synchronizations that bracket each one in between,
+        # so the GPU does not idle (and clock down) between them
+        torch.cuda.synchronize()
+        for events, _ in plan:
             t0 = time.perf_counter()
             sim.step(steps, force_events=iter(events))
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-        finally:
-            gc.enable()
-        times.append(t1 - t0)
-        force_ms += [e[0].elapsed_time(e[1]) for e in events if e is not None]
+            times.append(t1 - t0)
+    finally:
+        gc.enable()
+    force_ms = [a.elapsed_time(b) / m for _, pairs in plan for a, b, m in pairs]
     return statistics.median(times), times, force_ms, sim
 
 
@@ -657,7 +680,9 @@ def main():
                      "traffic": round(FORCE_TRAFFIC) if FORCE_TRAFFIC else None,
                      "valu_busy": FORCE_VALU_BUSY, "texture_addr_busy": FORCE_TA_BUSY,
                      "counters_from": FORCE_COUNTERS_FROM,
-                     "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3)},
+                     "bytes_per_launch": round(force_bytes), "avg_launch_us": round(force_ms * 1e3, 3),
+                     "launch_timing": f"HIP events around {EVENT_SPAN} consecutive chained launches "
+                                      f"per timed window, on the launch stream"},
     }
     checked, dangerous, dmax = sim.displacement_report()
     line["stale_list_check"] = {

@@ -282,8 +282,9 @@ class LJSim:
         FULL lists run one fused launch per step (ljmd_md_step_chained, or
         ljmd_md_step without chain); HALF lists run the separate force and
         integration calls.  force_events: optional iterator with one item per step,
-        a pre-created (start, end) timing-event pair recorded on the current stream
-        around that step's force launch, or None.  graphs: replay the steps between
+        a pre-created (start, end) pair of timing events recorded on the current stream
+        just before and just after that step's force launch (either may be None, so one
+        pair can span the launches of several steps), or None.  graphs: replay the steps between
         two rebuilds as one captured HIP graph (FULL lists, no timing events; bitwise
         the same trajectory as launching them one by one).  on_positions: optional callable
         given, for every step in order, the positions tensor the force call of that
@@ -331,12 +332,11 @@ class LJSim:
             else:
                 args = self._fused_args(energy)[1 if last else 0]
             ab = next(force_events) if force_events is not None else None
-            if ab is not None:
+            if ab is not None and ab[0] is not None:
                 ab[0].record()
-                _lib.check(mdstep(*args), name)
+            _lib.check(mdstep(*args), name)
+            if ab is not None and ab[1] is not None:
                 ab[1].record()
-            else:
-                _lib.check(mdstep(*args), name)
             if chain and last:
                 ops.md_step_sums(self.n, half, self._ws[ops.OP_MD_CHAIN], ev=self.ev)
             if on_positions is not None:
@@ -357,12 +357,11 @@ class LJSim:
                 self.rebuild()
                 kd, fc, kk, kkd = self._step_args(energy)
             ab = next(force_events) if force_events is not None else None
-            if ab is not None:
+            if ab is not None and ab[0] is not None:
                 ab[0].record()
-                _lib.check(forces(*fc), "ljmd_compute_forces")
+            _lib.check(forces(*fc), "ljmd_compute_forces")
+            if ab is not None and ab[1] is not None:
                 ab[1].record()
-            else:
-                _lib.check(forces(*fc), "ljmd_compute_forces")
             if on_positions is not None:
                 on_positions(self.x)
             # closing half kick of this step fused with the opening kick + drift of the
