@@ -106,6 +106,10 @@ extern "C" {
 #define LJMD_MAX_TYPES 8
 #define LJMD_TILE 64     /* atoms per neighbor-list tile: one wavefront */
 #define LJMD_MAX_TEAM 16 /* largest team (lanes per atom) of ljmd_compute_forces_csr */
+/* Tiled FULL-list forces (ljmd_compute_forces, ljmd_compute_forces_aosoa, the
+ * fused steps) take four lanes per atom up to this many atoms (one 128-atom
+ * block per compute unit), two beyond: the team size fixes the summation order. */
+#define LJMD_SMALL_GRID_ATOMS 32768
 
 typedef struct {
   double L[3]; /* box edges; periodic in all three dimensions, origin at 0 */
@@ -208,8 +212,9 @@ int ljmd_build_neighbors_csr(const ljmd_box *box, double rlist, int kind, int64_
  *   ev = { E = sum_i e_i, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz },  W = 1/2 sum_i sum_j d_ij (s d_ij)^T
  * (truncated, unshifted; one absolute rc for every type pair).
  *   precision  LJMD_FP64 or LJMD_MIXED
- *   kind       list kind built by ljmd_build_neighbors.  FULL: two lanes per
- *              atom, no atomics, bitwise deterministic.  HALF: Newton's third
+ *   kind       list kind built by ljmd_build_neighbors.  FULL: a team of
+ *              lanes per atom (four up to LJMD_SMALL_GRID_ATOMS atoms, else
+ *              two), no atomics, bitwise deterministic.  HALF: Newton's third
  *              law with FP64 atomic updates (summation order not fixed).
  *   ntypes     1..LJMD_MAX_TYPES; eps_packed/sigma_packed: device FP64
  *              [ntypes(ntypes+1)/2], upper triangle row-major:
@@ -403,8 +408,9 @@ int ljmd_list_to_csr(int64_t n, const int32_t *nbr, const int32_t *nnbr, int32_t
  * or a team of threads per particle; "Parallel Loops").  Lane t of a team takes
  * row entries t, t + team, ...; the team's sums are combined in a fixed
  * butterfly order, so results are bitwise deterministic.  ljmd_compute_forces
- * walks a FULL tiled list with teams of two, and with team == 2 the forces and
- * per-atom energies here are bitwise those (E and W agree to rounding).
+ * walks a FULL tiled list with teams of four up to LJMD_SMALL_GRID_ATOMS atoms
+ * and of two beyond; with the same team the forces and per-atom energies here
+ * are bitwise those (E and W agree to rounding).
  *   team     1, 2, 4, 8 or 16
  *   offsets, csr  as produced by ljmd_list_to_csr (entries must be in [0, n))
  *   ws       >= ljmd_workspace_bytes(LJMD_OP_FORCES_CSR, n, 0, ntypes) when

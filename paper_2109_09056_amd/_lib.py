@@ -23,6 +23,7 @@ SPME_MAX_GRID = 256
 MAX_TYPES = 8
 TILE = 64
 MAX_TEAM = 16
+SMALL_GRID_ATOMS = 32768  # tiled FULL-list forces: four lanes per atom up to here, then two
 NOALLOC_SCRATCH_BYTES = 2 << 20  # static scratch of ljmd_md_step_noalloc
 NOALLOC_MAX_ATOMS = 4194304
 

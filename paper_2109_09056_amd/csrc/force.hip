@@ -14,10 +14,11 @@
 // accumulation of F, e, E and W are FP64.  The pair energy u is taken in
 // FP64 from the FP32 reciprocal refined by one FP64 Newton step.
 //
-// FULL list: a team of two lanes owns atom i and walks its row of the tile
-// (row k of lane l of tile t at nbr[(t*maxn + k)*64 + l]; the team's lanes
-// take the even and the odd entries); no atomics, fixed summation order, so
-// the result is bitwise reproducible.  HALF list: the owner adds s*d to F_i in
+// FULL list: a team of lanes (two; four for grids of at most one block per
+// compute unit) owns atom i and walks its row of the tile (row k of lane l of
+// tile t at nbr[(t*maxn + k)*64 + l]; lane t of the team takes entries t,
+// t + team, ...); no atomics, fixed summation order, so the result is bitwise
+// reproducible.  HALF list: the owner adds s*d to F_i in
 // registers and subtracts it from F_j with FP64 hardware atomics.
 // Energy and virial: per-block partial sums in a fixed tree order, then one
 // column-sum launch (deterministic); in chained steps the first workgroup of
@@ -835,6 +836,17 @@ __global__ __launch_bounds__(kCsrThreads) void k_force_csr(ForceArgs a,
 constexpr int kUnroll = 8;
 constexpr int kTeam = 2;
 constexpr int kTeamUnroll = 6;
+// Up to LJMD_SMALL_GRID_ATOMS atoms (at most one 128-atom block per compute
+// unit) the tiled full-list kernels take four lanes per atom with 3 slots per
+// group: twice the waves in flight on a chip the grid leaves mostly idle.
+// Measured at 32,000 atoms: fused step 12.5 -> 11.6 us (FP64 12.1 -> 11.5),
+// forces with energy/virial 11.1 -> 10.1 us; from about 42,000 atoms (two
+// blocks per compute unit) on, four lanes gain nothing on the step, and at
+// 500,000 atoms the step takes 110 against 90 us.
+constexpr int64_t kSmallGridAtoms = LJMD_SMALL_GRID_ATOMS;
+constexpr int kSmallTeam = 4;
+constexpr int kSmallTeamUnroll = 3;
+static_assert(kSmallGridAtoms == 256 * kForceThreads, "one block per compute unit");
 
 // Half-list blocks: 256 home atoms (512 threads), 32 tile slots, 4 entries per group;
 // up to kHalfSmallAtoms atoms, blocks of 128 home atoms (twice the blocks for a chip
@@ -867,6 +879,22 @@ void launch_half(const ForceArgs &a, hipStream_t st) {
         <<<nb, kHalfAtoms * kHalfTeam, 0, st>>>(a);
 }
 
+// The tiled full-list kernel in the team shape for a.n atoms (every caller --
+// forces, AoSoA forces, fused step -- takes the same shape, so their sums agree
+// bitwise); nblk = force_blocks(a.n).
+template <bool MIXED, bool T1, bool EV, bool STEP, int V = 1>
+void launch_full(const ForceArgs &a, unsigned nblk, hipStream_t st) {
+  if (a.n <= kSmallGridAtoms)
+    k_force_full<MIXED, T1, EV, kSmallTeamUnroll, true, STEP, false, kSmallTeam, V>
+        <<<nblk, kForceThreads * kSmallTeam, 0, st>>>(a);
+  else if (V != 1 || a.n <= kNarrowAtoms)
+    k_force_full<MIXED, T1, EV, kTeamUnroll, true, STEP, false, kTeam, V>
+        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
+  else if constexpr (V == 1)
+    k_force_full<MIXED, T1, EV, kTeamUnroll, true, STEP, true, kTeam>
+        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
+}
+
 template <bool MIXED, bool T1, bool EV>
 void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
   if (kind == LJMD_HALF) {
@@ -874,12 +902,9 @@ void launch_one(const ForceArgs &a, int kind, unsigned nblk, hipStream_t st) {
       launch_half<MIXED, T1, EV, true>(a, st);
     else
       launch_half<MIXED, T1, EV, false>(a, st);
-  } else if (a.n <= kNarrowAtoms)
-    k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, false, kTeam>
-        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
-  else
-    k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, true, kTeam>
-        <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
+  } else {
+    launch_full<MIXED, T1, EV, false>(a, nblk, st);
+  }
 }
 
 template <bool MIXED>
@@ -1022,8 +1047,7 @@ int launch_forces_csr(const BoxK &b, int precision, double rc, int32_t ntypes, c
 namespace {
 template <bool MIXED, bool T1, bool EV, int V>
 void launch_aosoa_one(const ForceArgs &a, unsigned nblk, hipStream_t st) {
-  k_force_full<MIXED, T1, EV, kTeamUnroll, true, false, false, kTeam, V>
-      <<<nblk, kForceThreads * kTeam, 0, st>>>(a);
+  launch_full<MIXED, T1, EV, false, V>(a, nblk, st);
 }
 
 template <bool MIXED, int V>
@@ -1156,26 +1180,18 @@ int launch_md_step(const BoxK &b, int precision, double rc, int32_t ntypes, cons
   a.prev_rows = nblk;
   const bool mixed = precision == LJMD_MIXED;
   const bool t1 = ntypes == 1;
-#define LJMD_STEP(M, T)                                                                    \
-  do {                                                                                     \
-    if (n <= kNarrowAtoms)                                                                 \
-      k_force_full<M, T, true, kTeamUnroll, true, true, false, kTeam>                      \
-          <<<nblk, kForceThreads * kTeam, 0, st>>>(a);                                     \
-    else                                                                                   \
-      k_force_full<M, T, true, kTeamUnroll, true, true, true, kTeam>                       \
-          <<<nblk, kForceThreads * kTeam, 0, st>>>(a);                                     \
-  } while (0)
   if (n > 0) {
     if (mixed) {
-      if (t1) LJMD_STEP(true, true); else LJMD_STEP(true, false);
+      if (t1) launch_full<true, true, true, true>(a, nblk, st);
+      else launch_full<true, false, true, true>(a, nblk, st);
     } else {
-      if (t1) LJMD_STEP(false, true); else LJMD_STEP(false, false);
+      if (t1) launch_full<false, true, true, true>(a, nblk, st);
+      else launch_full<false, false, true, true>(a, nblk, st);
     }
   } else {
     k_zero_f64<<<1, 256, 0, st>>>(a.partial, kEvStride);
     if (prev_ev) k_colsum<1024><<<1, 1024, 0, st>>>(1, kEvStride, 8, prev_partial, prev_ev, 1.0, 0);
   }
-#undef LJMD_STEP
   if (ev) k_colsum<1024><<<1, 1024, 0, st>>>(nblk, kEvStride, 8, a.partial, ev, 1.0, 0);
   return check_launch("ljmd_md_step");
 }

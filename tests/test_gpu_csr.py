@@ -1,6 +1,6 @@
 """Compressed (CSR) neighbor lists and team-per-atom force traversal: rows equal to the
 tiled list they come from, forces and energies against the oracle for every team size,
-team 2 bitwise equal to the tiled kernel's forces, every team deterministic."""
+the tiled kernel's team bitwise equal to its forces, every team deterministic."""
 import numpy as np
 import pytest
 
@@ -23,7 +23,8 @@ def _case(name):
         rng = np.random.default_rng(11)
         L = np.array([12.0, 13.0, 14.0])
         return L, rng.uniform(0, 1, (1000, 3)) * L, np.zeros(1000, np.int32), [1.0], [1.0]
-    w = li.WORKLOADS[name]
+    # 70,304 atoms, two types: beyond the four-lane small-grid size of the tiled kernel
+    w = li.Workload("lj70k_2t", 7, cells=26, ntypes=2) if name == "lj70k_2t" else li.WORKLOADS[name]
     if w.ntypes == 1:
         return w.box, li.positions(w), np.zeros(w.natoms, np.int32), [1.0], [1.0]
     eps, sig = li.params(w)
@@ -115,21 +116,26 @@ def test_csr_forces_vs_oracle(dev, orc, name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_csr_team2_bitwise_tiled_and_teams_deterministic(dev, prec):
-    """The tiled kernel walks rows with two lanes per atom: CSR with team 2 gives bitwise
-    the same forces and per-atom energies; every team size is deterministic."""
+@pytest.mark.parametrize("name", ["lj32k_fm", "lj70k_2t"])
+def test_csr_team_bitwise_tiled_and_teams_deterministic(dev, prec, name):
+    """The tiled kernel walks rows with four lanes per atom up to SMALL_GRID_ATOMS atoms
+    (32,000 here) and two beyond (70,304): CSR with that team gives bitwise the same
+    forces and per-atom energies; every team size is deterministic."""
     import torch
-    from paper_2109_09056_amd import ops
-    sim = _sim(dev, "lj32k_fm")
+    from paper_2109_09056_amd import _lib, ops
+    sim = _sim(dev, name)
     nl = sim.nl
+    tiled_team = 4 if sim.n <= _lib.SMALL_GRID_ATOMS else 2
     P = ops.FP64 if prec == "fp64" else ops.MIXED
     off, csr = ops.list_to_csr(nl.nbr, nl.nnbr, nl.maxn)
     Ft, et, evt = ops.compute_forces(sim.L, P, ops.FULL, 2.5, sim.eps, sim.sigma, sim.x,
                                      sim.types, nl.nbr, nl.nnbr, nl.maxn)
     F2, e2, ev2 = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types,
-                                         off, csr, team=2)
+                                         off, csr, team=tiled_team)
     assert torch.equal(F2, Ft) and torch.equal(e2, et)
     np.testing.assert_allclose(ev2.cpu().numpy(), evt.cpu().numpy(), rtol=1e-12, atol=0)
+    if name != "lj32k_fm":
+        return
     for team in TEAMS:
         a = ops.compute_forces_csr(sim.L, P, 2.5, sim.eps, sim.sigma, sim.x, sim.types, off, csr,
                                    team=team)
