@@ -465,8 +465,8 @@ __global__ void k_zero_f64(double *p, int64_t m) {
   if (q < m) p[q] = 0.0;
 }
 
-// Half list (HALF): blocks of ATOMS consecutive sorted atoms, kHalfTeam lanes
-// per atom (lane t takes the row entries t, t + kHalfTeam, ...).  The owner of
+// Half list (HALF): blocks of ATOMS consecutive sorted atoms, TEAM lanes per
+// atom (lane t takes the row entries t, t + TEAM, ...).  The owner of
 // pair (i, j), j > i, keeps +s*d for F_i in registers and hands -s*d (and u/2
 // for e_j) to j through LDS: the block's j-side sums are kept per 64-atom tile
 // of sorted atoms, in SLOTS slots assigned at a tile's first touch by a small
@@ -476,7 +476,7 @@ __global__ void k_zero_f64(double *p, int64_t m) {
 // another wave has claimed but not yet published) adds its j-side through
 // direct global atomics.  Summation order is not fixed: HALF results are
 // reproducible to rounding, not bitwise.
-constexpr int kHalfTeam = 2;  // lanes per home atom
+constexpr int kHalfTeam = 2;  // lanes per home atom (large grids)
 constexpr int kHalfTabBits = 7;
 constexpr int kHalfTab = 1 << kHalfTabBits;  // table entries
 
@@ -575,15 +575,15 @@ __device__ __forceinline__ void half_pair(const ForceArgs &a, HalfLds<NV, SLOTS>
   }
 }
 
-// One lane's share of a half row: every kHalfTeam-th entry from `row`, in
-// groups of U (indices, then gathers, then pairs, as walk_row).
-template <bool MIXED, bool T1, bool EV, bool EATOM, bool WRAP, bool WIDE, int U, int NV,
-          int SLOTS>
+// One lane's share of a half row: every TEAM-th entry from `row`, in groups of
+// U (indices, then gathers, then pairs, as walk_row).
+template <bool MIXED, bool T1, bool EV, bool EATOM, bool WRAP, bool WIDE, int U, int TEAM,
+          int NV, int SLOTS>
 __device__ __forceinline__ void half_row(const ForceArgs &a, HalfLds<NV, SLOTS> &s,
                                          const int32_t *row, int32_t cnt, double xi, double yi,
                                          double zi, int ti, const Coef &c1, const double *tab,
                                          HalfAcc &r) {
-  constexpr int kStep = kHalfTeam * kWave;
+  constexpr int kStep = TEAM * kWave;
   int32_t ltile = -1, lslot = -1;
   for (int32_t k = 0; k < cnt; k += U, row += U * kStep) {
     int32_t j[U];
@@ -609,10 +609,11 @@ __device__ __forceinline__ void half_row(const ForceArgs &a, HalfLds<NV, SLOTS> 
   }
 }
 
-template <bool MIXED, bool T1, bool EV, bool EATOM, bool WIDE, int ATOMS, int SLOTS, int U>
-__global__ __launch_bounds__(ATOMS * kHalfTeam) void k_force_half(ForceArgs a) {
+template <bool MIXED, bool T1, bool EV, bool EATOM, bool WIDE, int ATOMS, int SLOTS, int U,
+          int TEAM = kHalfTeam>
+__global__ __launch_bounds__(ATOMS * TEAM) void k_force_half(ForceArgs a) {
   constexpr int NV = EATOM ? 4 : 3;
-  constexpr int kThreads = ATOMS * kHalfTeam;
+  constexpr int kThreads = ATOMS * TEAM;
   constexpr int kWaves = kThreads / kWave;
   __shared__ HalfLds<NV, SLOTS> s;
   __shared__ double tab[T1 ? 4 : 4 * LJMD_MAX_TYPES * LJMD_MAX_TYPES];
@@ -630,8 +631,8 @@ __global__ __launch_bounds__(ATOMS * kHalfTeam) void k_force_half(ForceArgs a) {
     load_table(a, tab);  // ends with a barrier
   }
   __syncthreads();
-  const int t = (int)threadIdx.x % kHalfTeam;
-  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * ATOMS + (int)threadIdx.x / kHalfTeam;
+  const int t = (int)threadIdx.x % TEAM;
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * ATOMS + (int)threadIdx.x / TEAM;
   const bool live = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0;
   if (live) {
@@ -647,17 +648,19 @@ __global__ __launch_bounds__(ATOMS * kHalfTeam) void k_force_half(ForceArgs a) {
   if (live) {
     const int ti = T1 ? 0 : a.type[i];
     const int32_t ctot = a.nnbr[i];
-    const int32_t cnt = ctot > t ? (ctot - t + kHalfTeam - 1) / kHalfTeam : 0;
+    const int32_t cnt = ctot > t ? (ctot - t + TEAM - 1) / TEAM : 0;
     const int32_t *row =
         a.nbr + (int64_t)(i >> 6) * a.maxn * kWave + (i & (kWave - 1)) + (int64_t)t * kWave;
     if (interior)
-      half_row<MIXED, T1, EV, EATOM, false, WIDE, U>(a, s, row, cnt, xi, yi, zi, ti, c1, tab, r);
+      half_row<MIXED, T1, EV, EATOM, false, WIDE, U, TEAM>(a, s, row, cnt, xi, yi, zi, ti, c1,
+                                                           tab, r);
     else
-      half_row<MIXED, T1, EV, EATOM, true, WIDE, U>(a, s, row, cnt, xi, yi, zi, ti, c1, tab, r);
+      half_row<MIXED, T1, EV, EATOM, true, WIDE, U, TEAM>(a, s, row, cnt, xi, yi, zi, ti, c1,
+                                                          tab, r);
   }
   const double e_lane = r.e;
 #pragma unroll
-  for (int mask = kHalfTeam / 2; mask > 0; mask >>= 1) {
+  for (int mask = TEAM / 2; mask > 0; mask >>= 1) {
     r.fx += __shfl_xor(r.fx, mask, kWave);
     r.fy += __shfl_xor(r.fy, mask, kWave);
     r.fz += __shfl_xor(r.fz, mask, kWave);
@@ -848,14 +851,23 @@ constexpr int kSmallTeam = 4;
 constexpr int kSmallTeamUnroll = 3;
 static_assert(kSmallGridAtoms == 256 * kForceThreads, "one block per compute unit");
 
-// Half-list blocks: 256 home atoms (512 threads), 32 tile slots, 4 entries per group;
-// up to kHalfSmallAtoms atoms, blocks of 128 home atoms (twice the blocks for a chip
-// of 256 compute units: 32,000 atoms 41 -> 35 us, 500,000 atoms 174 -> 179 us).
+// Half-list blocks: 256 home atoms with two lanes each (512 threads), 32 tile
+// slots, 4 entries per group.  Up to kHalfSmallAtoms atoms: blocks of 128 home
+// atoms with four lanes each (more blocks and more waves for grids that do not
+// fill the chip); up to LJMD_SMALL_GRID_ATOMS atoms (one block per compute
+// unit): eight lanes each and 48 slots.  Measured with per-atom energies and
+// virial (us): 32,000 atoms 38.0 (128 x 2) -> 28.0 (128 x 4) -> 23.2 (128 x 8,
+// 48 slots); 108,000 atoms 77.5 -> 61.7 (128 x 4; 256 x 2: 64.9); 256,000
+// atoms 153.4 -> 127.9 (256 x 2: 141.0); 500,000 atoms 256 x 2 234.2, 128 x 4
+// 236.3, 128 x 8 373.
 constexpr int kHalfAtoms = 256;
 constexpr int kHalfSmallBlock = 128;
 constexpr int64_t kHalfSmallAtoms = 262144;
 constexpr int kHalfSlots = 32;
 constexpr int kHalfUnroll = 4;
+constexpr int kHalfSmallTeam = 4;
+constexpr int kHalfTinyTeam = 8;
+constexpr int kHalfTinySlots = 48;
 
 int half_block_atoms(int64_t n) { return n <= kHalfSmallAtoms ? kHalfSmallBlock : kHalfAtoms; }
 
@@ -868,9 +880,12 @@ unsigned half_blocks(int64_t n) {
 template <bool MIXED, bool T1, bool EV, bool EATOM>
 void launch_half(const ForceArgs &a, hipStream_t st) {
   const unsigned nb = half_blocks(a.n);
-  if (a.n <= kHalfSmallAtoms)
-    k_force_half<MIXED, T1, EV, EATOM, false, kHalfSmallBlock, kHalfSlots, kHalfUnroll>
-        <<<nb, kHalfSmallBlock * kHalfTeam, 0, st>>>(a);
+  if (a.n <= kSmallGridAtoms)
+    k_force_half<MIXED, T1, EV, EATOM, false, kHalfSmallBlock, kHalfTinySlots, kHalfUnroll,
+                 kHalfTinyTeam><<<nb, kHalfSmallBlock * kHalfTinyTeam, 0, st>>>(a);
+  else if (a.n <= kHalfSmallAtoms)
+    k_force_half<MIXED, T1, EV, EATOM, false, kHalfSmallBlock, kHalfSlots, kHalfUnroll,
+                 kHalfSmallTeam><<<nb, kHalfSmallBlock * kHalfSmallTeam, 0, st>>>(a);
   else if (a.n <= kNarrowAtoms)
     k_force_half<MIXED, T1, EV, EATOM, false, kHalfAtoms, kHalfSlots, kHalfUnroll>
         <<<nb, kHalfAtoms * kHalfTeam, 0, st>>>(a);
