@@ -6,6 +6,7 @@
 //   1. cell id + histogram   one thread per atom; lanes of a wavefront in the
 //                            same cell share one atomic add and get ranks
 //   2. exclusive scan        one 1024-thread block over all cells, in chunks
+//                            (wavefront shuffle scans)
 //   3. scatter               one thread per atom to slot start[cell] + rank
 //   4. in-cell rank + permute  one wavefront per cell: ids of the cell are
 //                            staged in LDS, each lane ranks its atom among
@@ -72,46 +73,69 @@ __global__ void k_count(int64_t n, const double *__restrict__ x, GridK g,
   }
 }
 
+// Inclusive prefix sum of v over the lanes of the wavefront (shuffles only).
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
 // Exclusive scan of counts[0..m) into start[0..m] (start[m] = total).  One
-// block walks the cells in chunks of 4 * kScanThreads: coalesced loads, a
-// block scan in LDS, and a running carry between chunks.
+// block walks the cells in chunks of 4 * kScanThreads, kScanAhead chunks loaded
+// at once (one load latency per group of chunks): in a chunk each thread holds
+// four consecutive counts, the waves scan their threads' sums with shuffles,
+// and the wave totals meet in LDS (two barriers per chunk); a running carry
+// joins the chunks.
+constexpr int kScanAhead = 8;
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t m, const int32_t *__restrict__ counts,
                                                      int32_t *__restrict__ start) {
-  __shared__ int32_t part[kScanThreads];
-  __shared__ int32_t carry_s;
+  constexpr int kWaves = kScanThreads / kWave;
+  constexpr int32_t kChunk = 4 * kScanThreads;
+  __shared__ int32_t wsum[kWaves];
   const int t = threadIdx.x;
-  if (t == 0) carry_s = 0;
-  __syncthreads();
-  for (int32_t c0 = 0; c0 < m; c0 += 4 * kScanThreads) {
-    int32_t v[4];
-    int32_t s = 0;
+  const int lane = t & (kWave - 1), w = t / kWave;
+  int32_t carry = 0;  // the same in every thread
+  for (int32_t g0 = 0; g0 < m; g0 += kScanAhead * kChunk) {
+    int32_t v[kScanAhead][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int32_t c = c0 + 4 * t + q;
-      v[q] = c < m ? counts[c] : 0;
-      s += v[q];
-    }
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const int32_t o = t >= off ? part[t - off] : 0;
-      __syncthreads();
-      part[t] += o;
-      __syncthreads();
-    }
-    const int32_t carry = carry_s;
-    int32_t run = carry + part[t] - s;
+    for (int p = 0; p < kScanAhead; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int32_t c = c0 + 4 * t + q;
-      if (c < m) start[c] = run;
-      run += v[q];
+      for (int q = 0; q < 4; ++q) {
+        const int32_t c = g0 + p * kChunk + 4 * t + q;
+        v[p][q] = c < m ? counts[c] : 0;
+      }
+#pragma unroll
+    for (int p = 0; p < kScanAhead; ++p) {
+      const int32_t c0 = g0 + p * kChunk;
+      if (c0 >= m) break;  // block-uniform
+      const int32_t s = v[p][0] + v[p][1] + v[p][2] + v[p][3];
+      const int32_t inc = wave_inclusive_scan(s);
+      if (lane == kWave - 1) wsum[w] = inc;
+      __syncthreads();
+      int32_t before = 0, total = 0;
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k) {
+        const int32_t ws = wsum[k];
+        before += k < w ? ws : 0;
+        total += ws;
+      }
+      int32_t run = carry + before + inc - s;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t c = c0 + 4 * t + q;
+        if (c < m) start[c] = run;
+        run += v[p][q];
+      }
+      carry += total;
+      __syncthreads();  // wsum is written again by the next chunk
     }
-    __syncthreads();
-    if (t == kScanThreads - 1) carry_s = carry + part[t];
-    __syncthreads();
   }
-  if (t == 0) start[m] = carry_s;
+  if (t == 0) start[m] = carry;
 }
 
 // Slot of atom i: start of its cell plus its rank (no atomics).

@@ -465,6 +465,13 @@ __global__ void k_zero_f64(double *p, int64_t m) {
   if (q < m) p[q] = 0.0;
 }
 
+// p[0..m) = 0 and, when r is given, r[0..k) = 0, in one launch (k <= m).
+__global__ void k_zero2_f64(double *p, int64_t m, double *r, int64_t k) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) p[q] = 0.0;
+  if (r && q < k) r[q] = 0.0;
+}
+
 // Half list (HALF): blocks of ATOMS consecutive sorted atoms, TEAM lanes per
 // atom (lane t takes the row entries t, t + TEAM, ...).  The owner of
 // pair (i, j), j > i, keeps +s*d for F_i in registers and hands -s*d (and u/2
@@ -966,8 +973,7 @@ int launch_forces(const BoxK &b, int precision, int kind, double rc, int32_t nty
   const unsigned nblk = force_blocks(n);
   const bool want_ev = ev != nullptr || e_atom != nullptr;
   if (kind == LJMD_HALF) {
-    k_zero_f64<<<(unsigned)((3 * n + 255) / 256 + 1), 256, 0, st>>>(F, 3 * n);
-    if (e_atom) k_zero_f64<<<(unsigned)((n + 255) / 256 + 1), 256, 0, st>>>(e_atom, n);
+    k_zero2_f64<<<(unsigned)((3 * n + 255) / 256 + 1), 256, 0, st>>>(F, 3 * n, e_atom, n);
   }
   if (n > 0) {
     if (precision == LJMD_MIXED)

@@ -53,6 +53,10 @@ def initial_maxn(n, L, rlist, kind):
 class NeighborList:
     """Atoms sorted by cell plus their tiled-ELL Verlet list (library-owned indexing)."""
 
+    # A build may leave its longest-row check for later (defer=True) only while the
+    # last checked build's longest row left at least this many free slots per row.
+    HEADROOM = 8
+
     def __init__(self, L, rlist, kind=FULL, maxn=None, device=None):
         self.L = [float(v) for v in L]
         self.rlist = float(rlist)
@@ -62,26 +66,69 @@ class NeighborList:
         self.nbr = self.nnbr = self.cell_start = None
         self.max_count = None
         self.builds = 0
+        self.deferred = 0          # builds whose longest-row check was left for later
         self.overflows = 0
+        self.last_need = None      # longest row of the last checked build
+        self._host_need = None     # pinned copy of a deferred build's longest row
+        self._need_ready = None    # event recorded after that copy
+        self._pending = False
 
-    def build(self, x_sorted, cell_start):
-        """Build from cell-sorted positions; grow the row capacity until nothing is cut."""
+    def build(self, x_sorted, cell_start, defer=False):
+        """Build from cell-sorted positions; grow the row capacity until nothing is cut.
+
+        Reading the longest row back makes the host wait for the build, and the GPU then
+        idles until the host has queued the next launches.  With defer, and while the
+        last checked build left HEADROOM free slots per row, the count is instead copied
+        to pinned host memory in stream order and checked by check() -- at the next
+        build at the latest; a row cut there raises RuntimeError (a liquid's longest row
+        moves by a few entries between rebuilds, so the headroom covers it)."""
+        self.check()
         n = x_sorted.shape[0]
         if self.maxn is None:
             self.maxn = initial_maxn(n, self.L, self.rlist, self.kind)
-        while True:
+        nnbr = self.nnbr if self.nnbr is not None and self.nnbr.numel() == n else None
+        if defer and self.last_need is not None and self.last_need + self.HEADROOM <= self.maxn:
             self.nbr, self.nnbr, self.max_count = ops.build_neighbors(
-                self.L, self.rlist, self.kind, x_sorted, cell_start, self.maxn, self.nbr,
-                self.nnbr if self.nnbr is not None and self.nnbr.numel() == n else None,
+                self.L, self.rlist, self.kind, x_sorted, cell_start, self.maxn, self.nbr, nnbr,
                 self.max_count)
-            need = int(self.max_count.item())
-            if need <= self.maxn:
-                break
-            self.overflows += 1
-            self.maxn = int(math.ceil((need + 8) / 4.0) * 4)
-            self.nbr = None
+            if self._host_need is None:
+                self._host_need = torch.empty(1, dtype=torch.int32, pin_memory=True)
+                self._need_ready = torch.cuda.Event()
+            self._host_need.copy_(self.max_count, non_blocking=True)
+            self._need_ready.record()
+            self._pending = True
+            self.deferred += 1
+        else:
+            while True:
+                self.nbr, self.nnbr, self.max_count = ops.build_neighbors(
+                    self.L, self.rlist, self.kind, x_sorted, cell_start, self.maxn, self.nbr,
+                    nnbr, self.max_count)
+                need = int(self.max_count.item())
+                if need <= self.maxn:
+                    break
+                self.overflows += 1
+                self.maxn = int(math.ceil((need + 8) / 4.0) * 4)
+                self.nbr = nnbr = None
+            self.last_need = need
         self.cell_start = cell_start
         self.builds += 1
+        return self
+
+    def check(self, block=True):
+        """Check a deferred build's longest row against the row capacity (block=False:
+        only if the stream has already passed it).  Raises RuntimeError when the build
+        cut rows: forces computed from it missed pairs."""
+        if not self._pending or (not block and not self._need_ready.query()):
+            return self
+        self._need_ready.synchronize()
+        self._pending = False
+        need = int(self._host_need[0])
+        self.last_need = need
+        if need > self.maxn:
+            self.overflows += 1
+            raise RuntimeError(
+                f"neighbor list build {self.builds} cut rows: longest row {need} > capacity "
+                f"{self.maxn} (checked after the build; later forces missed pairs)")
         return self
 
 
@@ -178,8 +225,8 @@ class LJSim:
         self._alt = (self.x, self.v, self.types,
                      self.ids if self.ids is not None else torch.empty_like(io))
         self.x, self.v, self.types, self.ids = xo, vo, to, io
-        self.nl.build(self.x, self.cell_start)
         self._xref.copy_(self.x)
+        self.nl.build(self.x, self.cell_start, defer=True)
         self._have_ref = True
         self._fargs = {}
 
@@ -344,6 +391,7 @@ class LJSim:
             if not last:
                 self.x, self.xn = self.xn, self.x
             s += 1
+        self.nl.check(block=False)
         return self
 
     def _step_unfused(self, nsteps, energy, force_events, on_positions=None):
@@ -367,10 +415,12 @@ class LJSim:
             # closing half kick of this step fused with the opening kick + drift of the
             # next one (same operations, one pass); the call ends on a plain half kick
             _lib.check(integrate(*(kk if s == nsteps - 1 else kkd)), "ljmd_integrate")
+        self.nl.check(block=False)
         return self
 
     # ---------------------------------------------------------------- reports
     def thermo(self):
+        self.nl.check()
         ev = self.ev.cpu()
         ke = float(ev[7])
         pe = float(ev[0])

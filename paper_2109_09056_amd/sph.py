@@ -66,7 +66,9 @@ class SPHSim:
         self._alt = (self.x, self.v, None,
                      self.ids if self.ids is not None else torch.empty_like(io))
         self.x, self.v, self.ids = xo, vo, io
-        self.nl.build(self.x, self.cell_start)
+        # after the first build, the row-capacity check of each rebuild is left to the next
+        # one (or energy()), so the host does not wait for the GPU at every rebuild
+        self.nl.build(self.x, self.cell_start, defer=True)
 
     def forces(self, energy=False):
         """Density (and U when energy) then the pressure acceleration at the current x."""
@@ -103,10 +105,12 @@ class SPHSim:
             else:
                 self.forces()
                 ops.integrate(KICK_KICK_DRIFT, self.dt, 1.0, self.L, self.x, self.v, self.acc)
+        self.nl.check(block=False)
         return self
 
     def energy(self):
         """(kinetic m/2 sum v^2, internal U) as of the last step taken with energy (syncs)."""
+        self.nl.check()
         return self.mass * float(self.ke.item()), float(self.u.item())
 
     def in_caller_order(self, t):

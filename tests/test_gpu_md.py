@@ -371,3 +371,35 @@ def test_dangerous_build_check_vs_oracle(dev, orc, every, steps):
         assert max(missed) > 0 and dangerous == 2
     if every == 5:
         assert max(missed) == 0 and dangerous == 0
+
+
+def test_deferred_row_capacity_check(dev):
+    """LJSim rebuilds leave the longest-row check of a build to the next one (no host wait
+    per rebuild): the trajectory is bitwise the one checked (and waited for) at every
+    build, and a deferred build that cut rows raises RuntimeError at its check."""
+    import torch
+    from paper_2109_09056_amd import md, ops
+    w = li.WORKLOADS["lj32k"]
+    s = li.make_system(w)
+    runs = []
+    for headroom in (md.NeighborList.HEADROOM, 10 ** 6):  # deferred / checked at once
+        sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, device=dev)
+        sim.nl.HEADROOM = headroom
+        sim.load(s["x"], s["v"])
+        sim.step(45)
+        sim.thermo()
+        runs.append((sim.x.clone(), sim.v.clone(), sim.nl.builds, sim.nl.deferred,
+                     sim.nl.last_need, sim.nl.maxn, sim.nl.overflows))
+    (xa, va, ba, da, *ra), (xb, vb, bb, db, *rb) = runs
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+    assert ba == bb == 3 and da == 2 and db == 0 and ra == rb and ra[2] == 0
+    # a build cut at a capacity below its longest row, with the check deferred
+    xs, _, _, _, cs = ops.bin(w.box, w.rlist, torch.as_tensor(li.positions(w), device=dev))
+    nl = md.NeighborList(w.box, w.rlist, ops.FULL, device=dev).build(xs, cs)
+    need = nl.last_need
+    nl.maxn, nl.last_need = need - 4, 0
+    nl.build(xs, cs, defer=True)
+    assert nl.deferred == 1 and nl._pending
+    with pytest.raises(RuntimeError, match="cut rows"):
+        nl.check()
+    assert nl.overflows == 1 and nl.last_need == need

@@ -56,6 +56,8 @@ BIN_CASES = [
     ("lj256", None), ("lj32k", None), ("gas_ragged", (331, (6.0, 7.5, 9.0))),
     ("gas_one", (1, (6.0, 6.0, 6.0))), ("gas_five", (5, (9.0, 9.1, 9.2))),
     ("clump", None),
+    # 15,625 and 24,389 cells: the cell scan runs over several 4,096-cell chunks
+    ("gas_many_cells", (40000, (70.0, 71.0, 72.5))), ("lj500k", None),
 ]
 
 
