@@ -247,6 +247,10 @@ SYSTEMS = {
                             (np.arange(256) % 3).astype(np.int32),
                             np.array([1.0, 0.9, 1.1, 1.2, 0.8, 1.05]),
                             np.array([1.0, 0.95, 1.02, 1.05, 0.92, 0.97])),
+    # 70,304 atoms, two types: the kernels' mid-size shapes (two lanes per atom on the
+    # full list, 128-atom blocks with four lanes on the half list)
+    "lj70k_2t": lambda: (lambda w: (li.positions(w), w.box, li.types(w), *li.params(w)))(
+        li.Workload("lj70k_2t", 7, cells=26, ntypes=2)),
 }
 
 
