@@ -226,8 +226,18 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
 
 // Block -> (home cell, part): part p of nsplit takes the cell's home atoms
 // [len p / nsplit, len (p + 1) / nsplit) (each part stages the whole stencil).
+// The standard shape asks for 4 resident wavefronts per SIMD (at most 128
+// VGPRs: the full-list build needs 131 and keeps 3 otherwise; 2 registers
+// spill): 500k 299.5 -> 259.6 us, 256k 171.3 -> 153.4 us, 32k unchanged.
+// Fewer register slots reach the same occupancy without spills (11: 258.6 us)
+// but send more crowded cells to the unstaged path (10 slots: 32k 43 -> 148 us).
+// The dense shape asks for 3 (the full list needs 179 VGPRs, 2 per SIMD
+// otherwise; no spills at 166): the 512,000-particle SPH build 528.7 -> 496.7 us.
+template <int SLOTS>
+constexpr int build_occupancy() { return SLOTS <= kSlots ? 4 : 3; }
+
 template <bool HALF, int SLOTS, int ROWCAP, int MODE = kTiled>
-__global__ __launch_bounds__(kWave) void k_build(GridK g, BoxK b, double rl2,
+__global__ __launch_bounds__(kWave, build_occupancy<SLOTS>()) void k_build(GridK g, BoxK b, double rl2,
                                                  const double *__restrict__ x,
                                                  const int32_t *__restrict__ cell_start,
                                                  BuildOut o, int32_t *__restrict__ max_count,
