@@ -237,11 +237,10 @@ template <int SLOTS>
 constexpr int build_occupancy() { return SLOTS <= kSlots ? 4 : 3; }
 
 template <bool HALF, int SLOTS, int ROWCAP, int MODE = kTiled>
-__global__ __launch_bounds__(kWave, build_occupancy<SLOTS>()) void k_build(GridK g, BoxK b, double rl2,
-                                                 const double *__restrict__ x,
-                                                 const int32_t *__restrict__ cell_start,
-                                                 BuildOut o, int32_t *__restrict__ max_count,
-                                                 int nsplit) {
+__global__ __launch_bounds__(kWave, build_occupancy<SLOTS>())
+void k_build(GridK g, BoxK b, double rl2, const double *__restrict__ x,
+             const int32_t *__restrict__ cell_start, BuildOut o, int32_t *__restrict__ max_count,
+             int nsplit) {
   const int32_t maxn = o.maxn;
   __shared__ int32_t rs[27];
   __shared__ int32_t pre[28];
