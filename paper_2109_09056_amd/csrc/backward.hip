@@ -200,7 +200,10 @@ __global__ __launch_bounds__(kThreads * TEAM) void k_vjp(BwdArgs a) {
     // pointer; the last, partial group gathers only slots below cnt.  Row order
     // throughout, so the sums match one slot at a time.
     auto walk = [&](auto wrap) {
-      constexpr int U = 4;
+      // 3 slots per group: 99 VGPRs against 112-118 with 4, and at 256,000 atoms
+      // (two types) 96.2 -> 92.4 us mixed, 95.3 -> 92.1 us FP64; 2 slots or
+      // occupancy hints (5-6 waves per SIMD) gained nothing or spilled.
+      constexpr int U = 3;
       const int32_t whole = cnt - cnt % U;
       const int32_t *rp = row;
       int32_t k = 0;
