@@ -217,6 +217,9 @@ class LJSim:
         self._ndisp += 1
 
     def rebuild(self):
+        # the previous build's deferred row check first: if it raises, nothing of this
+        # rebuild has happened yet (positions still in the order the list belongs to)
+        self.nl.check()
         if self._have_ref:
             self._check_displacement()
         xo, vo, to, io, self.cell_start = ops.bin(

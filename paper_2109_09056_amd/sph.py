@@ -60,6 +60,7 @@ class SPHSim:
         return self
 
     def rebuild(self):
+        self.nl.check()  # the previous build's deferred row check, before anything moves
         xo, vo, _, io, self.cell_start = ops.bin(self.L, self.rlist, self.x, self.v, None,
                                                  self.ids, out=self._alt,
                                                  cell_start=self.cell_start)

@@ -403,3 +403,15 @@ def test_deferred_row_capacity_check(dev):
     with pytest.raises(RuntimeError, match="cut rows"):
         nl.check()
     assert nl.overflows == 1 and nl.last_need == need
+    # in a simulation the failed check surfaces at the next rebuild, before it moves anything
+    sim = md.LJSim(w.box, rc=w.rc, skin=w.skin, precision=ops.MIXED, device=dev)
+    sim.load(s["x"], s["v"])
+    sim.step(19)  # the rebuild at step 20 is the next one
+    # a deferred build that cuts rows (no force call reads the list after it: the
+    # row capacity changes only here, and the rebuild below raises)
+    sim.nl.maxn, sim.nl.last_need = sim.nl.last_need - 4, 0
+    sim.nl.build(sim.x, sim.cell_start, defer=True)
+    x_before, cs_before = sim.x.clone(), sim.cell_start.clone()
+    with pytest.raises(RuntimeError, match="cut rows"):
+        sim.rebuild()
+    assert torch.equal(sim.x, x_before) and torch.equal(sim.cell_start, cs_before)
