@@ -117,7 +117,20 @@ def gpu_lists(dev, x, L, rlist, kind, maxn=None):
     return nl, ids, xs
 
 
-NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny"]
+NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny", "slab"]
+
+
+def slab_positions():
+    """A jittered simple-cubic lattice at the liquid's number density (0.8442) in a
+    22 x 28 x 150 lattice-cell slab: 92,400 atoms, 8 x 10 x 56 binning cells at rlist 2.8
+    (unequal counts per axis), every row of the list and every force at that size."""
+    a = (1.0 / 0.8442) ** (1.0 / 3.0)
+    nx, ny, nz = 22, 28, 150
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"),
+                 axis=-1).reshape(-1, 3).astype(np.float64)
+    L = a * np.array([nx, ny, nz], dtype=np.float64)
+    x = (g + 0.5 + np.random.default_rng(29).uniform(-0.1, 0.1, g.shape)) * a
+    return np.mod(x, L), L
 
 
 def case_positions(name):
@@ -136,6 +149,8 @@ def case_positions(name):
     if name == "tiny":
         L = np.array([6.0, 6.0, 6.0])
         return gas(3, L, 23), L
+    if name == "slab":
+        return slab_positions()
     raise KeyError(name)
 
 
@@ -251,6 +266,7 @@ SYSTEMS = {
     # full list, 128-atom blocks with four lanes on the half list)
     "lj70k_2t": lambda: (lambda w: (li.positions(w), w.box, li.types(w), *li.params(w)))(
         li.Workload("lj70k_2t", 7, cells=26, ntypes=2)),
+    "slab": lambda: (*slab_positions(), None, [1.0], [1.0]),
 }
 
 
