@@ -60,6 +60,15 @@ __device__ __forceinline__ double recip64(double a) {
   return __builtin_fma(y, e, y);
 }
 
+// a^(-1/2) by the hardware estimate refined with Newton-Raphson steps
+// y <- y (3/2 - (a/2) y^2), each of which squares the relative error.
+__device__ __forceinline__ double rsqrt64(double a) {
+  const double h = 0.5 * a;
+  double y = __builtin_amdgcn_rsq(a);
+  y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+  return __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+}
+
 __device__ __forceinline__ float recip32(float a) {
   float y = __builtin_amdgcn_rcpf(a);
   float e = __builtin_fmaf(-a, y, 1.0f);
