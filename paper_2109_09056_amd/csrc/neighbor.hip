@@ -12,6 +12,10 @@
 // atom, a ballot + mbcnt prefix compacts the hits, and each hit is stored in
 // the home atom's row of the tiled-ELL list:
 //   nbr[((i / 64) * maxn + k) * 64 + (i % 64)].
+// On grids of 3 or more cells per dimension the candidates are staged as
+// 16-bit lattice coordinates and tested with packed integer arithmetic
+// (QuantK below); only pairs within the lattice's error band of rlist take the
+// FP64 test, so the lists are exactly those of the FP64 test everywhere.
 // Cells with more candidates than the register slots hold fall back to
 // reading candidates from global memory per home atom.
 #include "common.h"
@@ -28,7 +32,12 @@ constexpr int kSlots = 12;
 constexpr int kRowCap = 128;
 constexpr int kDenseSlots = 16;
 constexpr int kDenseRowCap = 256;
-constexpr int kBatch = 16;  // home atoms whose rows are buffered in LDS at once
+// Home atoms whose rows are buffered in LDS at once.  8 rather than 16 halves
+// the one-wavefront block's LDS, so more blocks fit on a compute unit: the
+// integer-tested build at 500,000 atoms went 230.5 -> 207.0 us (full list),
+// 200.9 -> 173.3 (half), 388.9 -> 240.2 (dense shape); 4 gave 213.7 / 178.4 /
+// 231.6.
+constexpr int kBatch = 8;
 constexpr int kFlushRows = kWave / kBatch;  // list rows of a batch written per store instruction
 // LDS row stride ROWCAP + 1 (odd): lanes reading entry k of different rows hit distinct banks
 
@@ -48,6 +57,53 @@ struct BuildOut {
   int32_t *csr;            // kCsr: rows
   int64_t cap;             // kCsr: capacity of csr
 };
+
+// Integer pre-test of the candidate distances (grids of at least 3 cells per
+// dimension).  Each staged position is taken relative to the home cell's
+// centre, minimum-imaged there and rounded to a lattice of spacing q: u =
+// rint(min_image(x - centre) / q), |u| <= kQuantMax (the 27 stencil cells lie
+// within 1.5 cell edges of the centre).  A pair's lattice displacement then
+// differs from the true one by at most q per axis, so its length by at most
+// sqrt(3) q, and with R = rlist / q the integer r2q = |u_i - u_j|^2 decides
+//   r2q < t_in  = floor((R - 1.75)^2): inside rlist,
+//   r2q > t_out = ceil((R + 1.75)^2):  outside rlist,
+// and only the pairs between (about 0.15 per atom in the dense liquid) take
+// the FP64 test with the minimum image.  The image of a candidate nearest the
+// centre is the one nearest the home atom for every pair within rlist when
+// the home atom lies within L/2 - rlist of the centre per axis (the pair is
+// then within L/2 of the centre); atoms inside their cell always do (cell
+// edges exceed rlist and nc >= 3), and a wavefront whose home atoms do not
+// (positions outside the box) takes the unstaged FP64 path.  So the lists are
+// exactly those of the FP64 test.
+struct QuantK {
+  double invq;     // 1 / q
+  int32_t t_in;    // r2q below: inside rlist
+  int32_t t_out;   // r2q above: outside rlist
+  double home[3];  // bound on |home atom - centre| per axis: L/2 - rlist, rounded down
+};
+constexpr double kQuantSpan = 8000.0;  // lattice steps per 1.5 cell edges
+constexpr int32_t kQuantMax = 8190;    // |u| of a staged coordinate
+// z of an empty slot: |dz| <= 33,190, so r2q stays below 2^31 and above t_out
+constexpr int32_t kQuantEmpty = 25000;
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// Lattice coordinates of x relative to the centre cc; false when a coordinate
+// is out of range (or not finite).
+__device__ __forceinline__ bool quantize(const double *p, const double *cc, const BoxK &b,
+                                         double invq, int32_t &uxy, int32_t &uz) {
+  int32_t u[3];
+  bool in = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = min_image(p[k] - cc[k], b.L[k], b.invL[k]) * invq;
+    in = in && __builtin_fabs(d) <= (double)kQuantMax;
+    u[k] = in ? (int32_t)__builtin_rint(d) : 0;
+  }
+  uxy = (int32_t)((uint32_t)(uint16_t)u[0] | ((uint32_t)u[1] << 16));
+  uz = u[2];
+  return in;
+}
 
 // Stencil of cell c: its candidate ranges [rs[s], rs[s] + len) in sorted order
 // and the prefix pre[s] of their lengths.  Returns the number of ranges.
@@ -224,23 +280,173 @@ __device__ __forceinline__ void build_staged(const BoxK &b, double rl2, const do
   }
 }
 
+// Store a hit of the lanes' ballot m: entry base + (hits in lower lanes) of the
+// home atom's row (LDS buffer, tiled row or compressed row).
+// room: base + popcount(m) <= maxn (uniform), so no lane needs its own test.
+template <bool BUF, int ROWCAP, int MODE>
+__device__ __forceinline__ void store_hit(const BuildOut &o, int32_t *row, int32_t *rowbuf, int bi,
+                                          int64_t off, int32_t base, uint64_t m, bool room,
+                                          int32_t j, int32_t maxn) {
+  const int32_t k = (int32_t)__builtin_amdgcn_mbcnt_hi(
+      (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
+  if constexpr (MODE == kCsr) {
+    if (off + k < o.cap) o.csr[off + k] = j;
+  } else if (room) {
+    if (BUF)
+      rowbuf[bi * (ROWCAP + 1) + k] = j;
+    else
+      row[(int64_t)k * kWave] = j;
+  } else if (k < maxn) {
+    if (BUF)
+      rowbuf[bi * (ROWCAP + 1) + k] = j;
+    else
+      row[(int64_t)k * kWave] = j;
+  }
+}
+
+// Register-staged build with the integer pre-test (QuantK): three registers
+// per slot (packed x/y lattice coordinates, z, index) instead of seven.  Same
+// rows in the same order as build_staged.  Returns false, having written
+// nothing, when a staged coordinate is out of range (positions outside the
+// box); the caller then takes the unstaged path.
+template <bool HALF, bool BUF, int SLOTS, int ROWCAP, int MODE>
+__device__ __forceinline__ bool build_quant(const BoxK &b, const QuantK &q, const double *cc,
+                                            double rl2, const double *__restrict__ x, int32_t h0,
+                                            int32_t h1, int32_t total, int nslot,
+                                            const int32_t *rs, const int32_t *pre,
+                                            const BuildOut &o, int32_t *rowbuf, int32_t *rowcnt,
+                                            int32_t &maxc) {
+  const int32_t maxn = o.maxn;
+  int32_t *__restrict__ nbr = o.nbr;
+  int32_t *__restrict__ nnbr = o.nnbr;
+  static_assert(!BUF || MODE == kTiled, "rows are buffered only for the tiled list");
+  const int lane = threadIdx.x & (kWave - 1);
+  constexpr int kRowStride = ROWCAP + 1;
+  int32_t qxy[SLOTS], qz[SLOTS], qj[SLOTS];
+  bool good = true;
+#pragma unroll
+  for (int r = 0; r < SLOTS; ++r) {
+    const int32_t t = r * kWave + lane;
+    qj[r] = -1;
+    qxy[r] = 0;
+    qz[r] = kQuantEmpty;
+    if (r < nslot && t < total) {
+      const int32_t j = locate(t, rs, pre);
+      qj[r] = j;
+      good = quantize(x + 3 * (int64_t)j, cc, b, q.invq, qxy[r], qz[r]) && good;
+    }
+  }
+  for (int32_t c0 = h0; c0 < h1; c0 += kWave) {
+    const int32_t ih = c0 + lane;
+    if (ih < h1) {
+      const double *p = x + 3 * (int64_t)ih;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        good = good && __builtin_fabs(min_image(p[k] - cc[k], b.L[k], b.invL[k])) <= q.home[k];
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(!good) != 0) return false;
+  // candidate number of home atom h0: the home cell lies in one stencil range
+  // (ranges are disjoint on grids of 3 or more cells per dimension)
+  int32_t tc = 0;
+  for (int sr = 0; pre[sr] < total; ++sr)
+    if (rs[sr] <= h0 && h0 < rs[sr] + (pre[sr + 1] - pre[sr])) tc = pre[sr] + (h0 - rs[sr]);
+  double hx = 0.0, hy = 0.0, hz = 0.0;
+  int32_t hxy = 0, huz = 0;
+  for (int32_t b0 = h0; b0 < h1; b0 += kBatch) {
+    const int nb = h1 - b0 < kBatch ? h1 - b0 : kBatch;
+    if ((b0 - h0) % kWave == 0) {
+      const int32_t ih = b0 + lane;
+      if (ih < h1) {
+        const double *p = x + 3 * (int64_t)ih;
+        hx = p[0];
+        hy = p[1];
+        hz = p[2];
+        quantize(p, cc, b, q.invq, hxy, huz);  // a staged candidate: in range
+      }
+    }
+    for (int bi = 0; bi < nb; ++bi) {
+      const int32_t i = b0 + bi;
+      const int src = (b0 - h0) % kWave + bi;
+      const short2v ui = __builtin_bit_cast(short2v, __builtin_amdgcn_readlane(hxy, src));
+      const int32_t uzi = __builtin_amdgcn_readlane(huz, src);
+      int32_t *row = MODE == kTiled ? nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1))
+                                    : nullptr;
+      const int64_t off = MODE == kCsr ? o.offsets[i] : 0;
+      const int32_t tself = tc + (i - h0);  // candidate number of atom i
+      int32_t base = 0;
+#pragma unroll
+      for (int r = 0; r < SLOTS; ++r) {
+        if (r < nslot) {
+          const short2v d = __builtin_bit_cast(short2v, qxy[r]) - ui;
+          const int32_t dz = qz[r] - uzi;
+          const int32_t r2q = __builtin_amdgcn_sdot2(d, d, __mul24(dz, dz), false);
+          // lane masks of single compares (one v_cmp each) combined in scalar
+          // registers; the full list drops atom i itself by its lane bit
+          uint64_t keep;
+          if constexpr (HALF)
+            keep = __builtin_amdgcn_ballot_w64(qj[r] > i);
+          else
+            keep = r == (tself >> 6) ? ~(1ull << (tself & (kWave - 1))) : ~0ull;
+          uint64_t m = __builtin_amdgcn_ballot_w64(r2q < q.t_in) & keep;
+          const uint64_t m_near = __builtin_amdgcn_ballot_w64(r2q <= q.t_out) & keep & ~m;
+          if (m_near != 0) {
+            // the FP64 test with the minimum image for the pairs near rlist, on
+            // every lane (lanes not near read atom i)
+            const bool near = __builtin_amdgcn_inverse_ballot_w64(m_near);
+            const double xi = readlane_f64(hx, src), yi = readlane_f64(hy, src),
+                         zi = readlane_f64(hz, src);
+            const double *p = x + 3 * (int64_t)(near ? qj[r] : i);
+            const double dx = min_image(xi - p[0], b.L[0], b.invL[0]);
+            const double dy = min_image(yi - p[1], b.L[1], b.invL[1]);
+            const double dzz = min_image(zi - p[2], b.L[2], b.invL[2]);
+            m |= __builtin_amdgcn_ballot_w64(dist2(dx, dy, dzz) < rl2) & m_near;
+          }
+          const int32_t b0 = base;
+          base += (int32_t)__popcll(m);
+          const bool room = base <= maxn;
+          if (MODE != kCount && __builtin_amdgcn_inverse_ballot_w64(m))
+            store_hit<BUF, ROWCAP, MODE>(o, row, rowbuf, bi, off, b0, m, room, qj[r], maxn);
+        }
+      }
+      if (lane == 0) rowcnt[bi] = MODE == kTiled ? (base < maxn ? base : maxn) : base;
+      maxc = base > maxc ? base : maxc;
+    }
+    __syncthreads();  // rowbuf / rowcnt written by other lanes of this one-wavefront block
+    if (MODE != kCsr && lane < nb) nnbr[b0 + lane] = rowcnt[lane];
+    if (BUF) {
+      const int a = lane % kBatch;
+      const int32_t mine = a < nb ? rowcnt[a] : 0;
+      const int32_t kmax = wave_max(mine);
+      const int32_t i = b0 + a;
+      int32_t *row = nbr + (int64_t)(i >> 6) * maxn * kWave + (i & (kWave - 1));
+      for (int32_t k = lane / kBatch; k < kmax; k += kFlushRows)
+        if (k < mine) row[(int64_t)k * kWave] = rowbuf[a * kRowStride + k];
+    }
+    __syncthreads();  // before the next batch overwrites rowbuf / rowcnt
+  }
+  return true;
+}
+
 // Block -> (home cell, part): part p of nsplit takes the cell's home atoms
 // [len p / nsplit, len (p + 1) / nsplit) (each part stages the whole stencil).
-// The standard shape asks for 4 resident wavefronts per SIMD (at most 128
-// VGPRs: the full-list build needs 131 and keeps 3 otherwise; 2 registers
-// spill): 500k 299.5 -> 259.6 us, 256k 171.3 -> 153.4 us, 32k unchanged.
-// Fewer register slots reach the same occupancy without spills (11: 258.6 us)
-// but send more crowded cells to the unstaged path (10 slots: 32k 43 -> 148 us).
-// The dense shape asks for 3 (the full list needs 179 VGPRs, 2 per SIMD
-// otherwise; no spills at 166): the 512,000-particle SPH build 528.7 -> 496.7 us.
+// QUANT: integer pre-test (grids of 3 or more cells per dimension); 76-93
+// VGPRs, so residency is set by the LDS row buffer.  Against the FP64-staged
+// kernel on the same lists at 500,000 atoms: 259 -> 207 us (full), 243 -> 173
+// us (half), 390 -> 240 us (dense shape).
+// FP64-staged kernel (smaller grids): the standard shape asks for 4 resident
+// wavefronts per SIMD (at most 128 VGPRs: the full-list build needs 131 and
+// keeps 3 otherwise; 2 registers spill), which took the 500k build from 299.5
+// to 259.6 us when this kernel served every grid; the dense shape asks for 3
+// (179 VGPRs otherwise, no spills at 166).
 template <int SLOTS>
 constexpr int build_occupancy() { return SLOTS <= kSlots ? 4 : 3; }
 
-template <bool HALF, int SLOTS, int ROWCAP, int MODE = kTiled>
-__global__ __launch_bounds__(kWave, build_occupancy<SLOTS>())
+template <bool HALF, int SLOTS, int ROWCAP, int MODE = kTiled, bool QUANT = false>
+__global__ __launch_bounds__(kWave, QUANT ? 1 : build_occupancy<SLOTS>())
 void k_build(GridK g, BoxK b, double rl2, const double *__restrict__ x,
              const int32_t *__restrict__ cell_start, BuildOut o, int32_t *__restrict__ max_count,
-             int nsplit) {
+             int nsplit, QuantK q) {
   const int32_t maxn = o.maxn;
   __shared__ int32_t rs[27];
   __shared__ int32_t pre[28];
@@ -268,7 +474,23 @@ void k_build(GridK g, BoxK b, double rl2, const double *__restrict__ x,
     for (int k = 0; k < 3; ++k)
       wrap |= g.nc[k] < 4 || cc[k] == 0 || cc[k] == g.nc[k] - 1;
   }
-  if (nslot <= SLOTS) {
+  bool staged = false;
+  if constexpr (QUANT) {
+    if (nslot <= SLOTS) {
+      const int32_t cc3[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+      const double cc[3] = {(cc3[0] + 0.5) * g.h[0], (cc3[1] + 0.5) * g.h[1],
+                            (cc3[2] + 0.5) * g.h[2]};
+#define LJMD_QUANT(B)                                                                            \
+  build_quant<HALF, B, SLOTS, ROWCAP, MODE>(b, q, cc, rl2, x, h0, h1, total, nslot, rs, pre, o, \
+                                            rowbuf, rowcnt, maxc)
+      if constexpr (MODE == kTiled)
+        staged = maxn <= ROWCAP ? LJMD_QUANT(true) : LJMD_QUANT(false);
+      else
+        staged = LJMD_QUANT(false);
+#undef LJMD_QUANT
+    }
+  } else if (nslot <= SLOTS) {
+    staged = true;
 #define LJMD_STAGED(W, B)                                                                     \
   build_staged<HALF, W, B, SLOTS, ROWCAP, MODE>(b, rl2, x, h0, h1, total, nslot, rs, pre, o, \
                                                 rowbuf, rowcnt, maxc)
@@ -282,7 +504,8 @@ void k_build(GridK g, BoxK b, double rl2, const double *__restrict__ x,
       if (wrap) LJMD_STAGED(true, false); else LJMD_STAGED(false, false);
     }
 #undef LJMD_STAGED
-  } else {
+  }
+  if (!staged) {
     const double L0 = b.L[0], L1 = b.L[1], L2 = b.L[2];
     const double iL0 = b.invL[0], iL1 = b.invL[1], iL2 = b.invL[2];
     for (int32_t i = h0; i < h1; ++i) {
@@ -343,6 +566,31 @@ int build_split(int64_t ncells) {
   return (int)(s < kMaxSplit ? s : kMaxSplit);
 }
 
+// Lattice and thresholds of the integer pre-test for this grid and cutoff.
+QuantK make_quant(const GridK &g, const BoxK &b, double rl2) {
+  const double h = fmax(g.h[0], fmax(g.h[1], g.h[2]));
+  QuantK q;
+  q.invq = kQuantSpan / (1.5 * h);
+  const double R = sqrt(rl2) * q.invq;  // <= kQuantSpan / 1.5: cell edges exceed rlist
+  q.t_in = (int32_t)floor((R - 1.75) * (R - 1.75));
+  q.t_out = (int32_t)ceil((R + 1.75) * (R + 1.75));
+  for (int k = 0; k < 3; ++k) q.home[k] = (0.5 * b.L[k] - sqrt(rl2)) * (1.0 - 1e-12);
+  return q;
+}
+
+template <bool HALF, int SLOTS, int ROWCAP, int MODE>
+void launch_shape(const GridK &g, const BoxK &b, double rl2, const double *x,
+                  const int32_t *cell_start, const BuildOut &o, int32_t *max_count, int ns,
+                  hipStream_t st) {
+  const unsigned nblk = (unsigned)(g.ncells * ns);
+  if (g.nc[0] >= 3 && g.nc[1] >= 3 && g.nc[2] >= 3)
+    k_build<HALF, SLOTS, ROWCAP, MODE, true><<<nblk, kWave, 0, st>>>(
+        g, b, rl2, x, cell_start, o, max_count, ns, make_quant(g, b, rl2));
+  else
+    k_build<HALF, SLOTS, ROWCAP, MODE, false><<<nblk, kWave, 0, st>>>(
+        g, b, rl2, x, cell_start, o, max_count, ns, QuantK{});
+}
+
 template <int MODE>
 void launch_mode(const GridK &g, const BoxK &b, double rl2, bool half, const double *x,
                  const int32_t *cell_start, const BuildOut &o, int32_t *max_count,
@@ -350,18 +598,16 @@ void launch_mode(const GridK &g, const BoxK &b, double rl2, bool half, const dou
   const int ns = build_split(g.ncells);
   if (MODE != kTiled || o.maxn <= kRowCap) {
     if (half)
-      k_build<true, kSlots, kRowCap, MODE><<<g.ncells * ns, kWave, 0, st>>>(g, b, rl2, x, cell_start, o,
-                                                                      max_count, ns);
+      launch_shape<true, kSlots, kRowCap, MODE>(g, b, rl2, x, cell_start, o, max_count, ns, st);
     else
-      k_build<false, kSlots, kRowCap, MODE><<<g.ncells * ns, kWave, 0, st>>>(g, b, rl2, x, cell_start,
-                                                                       o, max_count, ns);
+      launch_shape<false, kSlots, kRowCap, MODE>(g, b, rl2, x, cell_start, o, max_count, ns, st);
   } else {
     if (half)
-      k_build<true, kDenseSlots, kDenseRowCap, MODE><<<g.ncells * ns, kWave, 0, st>>>(
-          g, b, rl2, x, cell_start, o, max_count, ns);
+      launch_shape<true, kDenseSlots, kDenseRowCap, MODE>(g, b, rl2, x, cell_start, o, max_count,
+                                                          ns, st);
     else
-      k_build<false, kDenseSlots, kDenseRowCap, MODE><<<g.ncells * ns, kWave, 0, st>>>(
-          g, b, rl2, x, cell_start, o, max_count, ns);
+      launch_shape<false, kDenseSlots, kDenseRowCap, MODE>(g, b, rl2, x, cell_start, o, max_count,
+                                                           ns, st);
   }
 }
 

@@ -117,7 +117,21 @@ def gpu_lists(dev, x, L, rlist, kind, maxn=None):
     return nl, ids, xs
 
 
-NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny", "slab"]
+NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny", "slab",
+             "cutoff_lattice"]
+
+
+def cutoff_lattice():
+    """Simple-cubic lattice of spacing rlist / 2 = 1.4 on 16^3 sites (7 binning cells per
+    axis), every coordinate moved by at most 1e-9: each atom's six second-axis neighbours
+    sit at rlist to within ~3e-9, so about half of those pairs are in the list and which
+    ones is decided by FP64 rounding -- the build's integer pre-test must hand every such
+    pair to the FP64 test."""
+    a = 1.4
+    g = np.stack(np.meshgrid(*[np.arange(16)] * 3, indexing="ij"), axis=-1).reshape(-1, 3)
+    L = np.full(3, 16 * a)
+    x = (g + 0.5) * a + np.random.default_rng(31).uniform(-1e-9, 1e-9, g.shape)
+    return np.mod(x, L), L
 
 
 def slab_positions():
@@ -151,6 +165,8 @@ def case_positions(name):
         return gas(3, L, 23), L
     if name == "slab":
         return slab_positions()
+    if name == "cutoff_lattice":
+        return cutoff_lattice()
     raise KeyError(name)
 
 
@@ -195,9 +211,61 @@ def test_neighbor_sets_dense_build_shape(dev, orc, case, kind):
     assert np.array_equal(got, oracle_pairs(off, nb, half=(kind == "half")))
 
 
-def test_neighbor_capacity_overflow_reported(dev, orc):
+def stencil_pairs(x, L, rlist):
+    """(i, j) pairs, i != j, that the cell build tests when positions may lie outside
+    [0, L): atom j's cell (floor(x / h), clamped to the grid as binning clamps it) is one
+    of the 27 around atom i's cell, and the minimum-image r^2 = (dx^2 + dy^2) + dz^2 is
+    below rlist^2.  For positions inside the box this is every pair within rlist."""
+    L = np.asarray(L, dtype=np.float64)
+    nc = np.floor(L / rlist).astype(np.int64)
+    for k in range(3):
+        while nc[k] > 1 and L[k] / nc[k] < rlist * (1.0 + 1e-10):
+            nc[k] -= 1
+    h = L / nc
+    cell = np.clip(np.floor(x / h).astype(np.int64), 0, nc - 1)
+    n = x.shape[0]
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    dc = (cell[i] - cell[j]) % nc
+    adj = np.all((dc == 0) | (dc == 1) | (dc == nc - 1), axis=1) & (i != j)
+    d = x[i] - x[j]
+    d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    keep = adj & (r2 < rlist * rlist)
+    return i[keep], j[keep]
+
+
+@pytest.mark.parametrize("kind", ["full", "half"])
+def test_neighbor_sets_positions_outside_the_box(dev, kind):
+    """Outside the documented range (positions in [0, L) at build time): atoms up to 1.4
+    cell edges beyond a face are binned into the face cells.  The build then matches the
+    stencil-restricted FP64 test exactly -- the wavefronts that see such atoms leave the
+    integer pre-test for the FP64 path."""
     from paper_2109_09056_amd import ops
-    w = li.WORKLOADS["lj256"]
+    L = np.array([15.0, 16.0, 17.0])
+    x = li.random_gas(2000, L, 37)
+    h = L / np.array([5, 5, 6])
+    x[:40, 0] = L[0] + np.linspace(0.05, 1.4, 40) * h[0]
+    x[40:60, 2] = -np.linspace(0.05, 1.4, 20) * h[2]
+    k = ops.FULL if kind == "full" else ops.HALF
+    nl, ids, _ = gpu_lists(dev, x, L, 2.8, k)
+    got = gpu_pairs_by_id(nl.nbr.cpu().numpy(), nl.nnbr.cpu().numpy(), nl.maxn,
+                          ids.cpu().numpy(), half=(kind == "half"))
+    i, j = stencil_pairs(x, L, 2.8)
+    if kind == "half":
+        i, j = np.minimum(i, j), np.maximum(i, j)
+        a = np.unique(np.stack([i, j], 1), axis=0)
+        i, j = a[:, 0], a[:, 1]
+    from helpers import pair_array
+    assert np.array_equal(got, pair_array(i, j))
+
+
+@pytest.mark.parametrize("case", ["lj256", "lj32k"])
+def test_neighbor_capacity_overflow_reported(dev, orc, case):
+    """Rows cut at maxn = 10 keep true neighbours and report the longest row: on a
+    2-cell grid (FP64-staged build) and an 11-cell grid (integer pre-test)."""
+    from paper_2109_09056_amd import ops
+    w = li.WORKLOADS[case]
     x = li.positions(w)
     xs, _, _, ids, cs = gpu_sort(dev, x, w.box, w.rlist)
     nbr, nnbr, mc = ops.build_neighbors(w.box, w.rlist, ops.FULL, xs, cs, 10)
