@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # gives the two counters); set to None whenever the kernel changes until re-measured.
 FORCE_COUNTERS_FROM = ("profiles/k_force_full_step_lj500k_hbm_counters.txt and "
                        "..._pipeline_counters.txt (rocprofv3 --pmc on this kernel build)")
-FORCE_TRAFFIC = 234.53e6
-FORCE_VALU_BUSY = 0.539
-FORCE_TA_BUSY = 0.763
+FORCE_TRAFFIC = 234.56e6
+FORCE_VALU_BUSY = 0.540
+FORCE_TA_BUSY = 0.766
 
 
 def log(msg):

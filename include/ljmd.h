@@ -164,6 +164,11 @@ int ljmd_bin(const ljmd_box *box, double rlist, int64_t n, const double *x_in,
  *
  * kind LJMD_FULL: N(i) = { j != i : r^2_ij < rlist^2 }.
  * kind LJMD_HALF: the pairs of the full relation with j > i (sorted indices).
+ * r^2_ij is the FP64 (dx*dx + dy*dy) + dz*dz of the minimum-image
+ * displacement.  The kernel settles most pairs with an integer test on 16-bit
+ * lattice coordinates about each cell's centre, whose error bound keeps it to
+ * pairs clearly inside or outside rlist; every other pair takes the FP64 test,
+ * so each decision is that test's.
  * Storage is tiled ELL, one tile per 64 consecutive sorted atoms:
  *   neighbor k of atom i is nbr[((i / 64) * maxn + k) * 64 + (i % 64)], k < nnbr[i]
  * so nbr holds ceil(n/64)*64*maxn int32 (sorted indices).  Order inside a row
