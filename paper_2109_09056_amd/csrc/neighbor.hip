@@ -307,8 +307,9 @@ __device__ __forceinline__ void store_hit(const BuildOut &o, int32_t *row, int32
 // Register-staged build with the integer pre-test (QuantK): three registers
 // per slot (packed x/y lattice coordinates, z, index) instead of seven.  Same
 // rows in the same order as build_staged.  Returns false, having written
-// nothing, when a staged coordinate is out of range (positions outside the
-// box); the caller then takes the unstaged path.
+// nothing, when a staged coordinate or a home atom is outside the bounds the
+// pre-test needs (positions outside the box); the caller then takes the
+// unstaged path.
 template <bool HALF, bool BUF, int SLOTS, int ROWCAP, int MODE>
 __device__ __forceinline__ bool build_quant(const BoxK &b, const QuantK &q, const double *cc,
                                             double rl2, const double *__restrict__ x, int32_t h0,
@@ -402,11 +403,11 @@ __device__ __forceinline__ bool build_quant(const BoxK &b, const QuantK &q, cons
             const double dzz = min_image(zi - p[2], b.L[2], b.invL[2]);
             m |= __builtin_amdgcn_ballot_w64(dist2(dx, dy, dzz) < rl2) & m_near;
           }
-          const int32_t b0 = base;
+          const int32_t k0 = base;  // row entries before this slot's hits
           base += (int32_t)__popcll(m);
           const bool room = base <= maxn;
           if (MODE != kCount && __builtin_amdgcn_inverse_ballot_w64(m))
-            store_hit<BUF, ROWCAP, MODE>(o, row, rowbuf, bi, off, b0, m, room, qj[r], maxn);
+            store_hit<BUF, ROWCAP, MODE>(o, row, rowbuf, bi, off, k0, m, room, qj[r], maxn);
         }
       }
       if (lane == 0) rowcnt[bi] = MODE == kTiled ? (base < maxn ? base : maxn) : base;
