@@ -118,7 +118,7 @@ def gpu_lists(dev, x, L, rlist, kind, maxn=None):
 
 
 NBR_CASES = ["lj256", "lj32k", "gas_ragged", "gas_long", "clump", "tiny", "slab",
-             "cutoff_lattice"]
+             "cutoff_lattice", "gas_three_cells", "gas_tight_cells"]
 
 
 def cutoff_lattice():
@@ -167,6 +167,15 @@ def case_positions(name):
         return slab_positions()
     if name == "cutoff_lattice":
         return cutoff_lattice()
+    if name == "gas_three_cells":
+        # 3 x 3 x 4 binning cells: the fewest per axis that take the build's integer
+        # pre-test, where the stencil wraps on every side
+        L = np.array([8.5, 8.9, 11.5])
+        return gas(800, L, 41), L
+    if name == "gas_tight_cells":
+        # 3 x 3 x 4 cells whose edge exceeds rlist = 2.8 by 1e-7
+        L = np.array([8.4000003, 8.4000003, 11.2000004])
+        return gas(700, L, 43), L
     raise KeyError(name)
 
 
