@@ -362,10 +362,12 @@ def traversal_study(w, sim, reps=50):
     from paper_2109_09056_amd import md
     hl = md.NeighborList(sim.L, sim.rlist, ops.HALF, device=sim.device).build(sim.x,
                                                                             sim.cell_start)
+    # with per-atom energies, and with E and W only
     for name, ea in (("half_list_us", e), ("half_list_no_eatom_us", None)):
         out[name] = round(event_time(lambda: ops.compute_forces(
             w.box, ops.MIXED, ops.HALF, w.rc, sim.eps, sim.sigma, sim.x, sim.types, hl.nbr,
-            hl.nnbr, hl.maxn, F=F, e_atom=ea, ev=ev, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)
+            hl.nnbr, hl.maxn, F=F, e_atom=ea, ev=ev, ws=sim._ws[ops.OP_FORCES],
+            atom_energy=ea is not None), reps) * 1e3, 2)
     out["tiled_team2_forces_only_us"] = round(event_time(lambda: ops.compute_forces(
         w.box, ops.MIXED, ops.FULL, w.rc, sim.eps, sim.sigma, sim.x, sim.types, nl.nbr,
         nl.nnbr, nl.maxn, F=F, want_energy=False, ws=sim._ws[ops.OP_FORCES]), reps) * 1e3, 2)

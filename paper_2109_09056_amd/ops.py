@@ -121,8 +121,10 @@ def build_neighbors(L, rlist, kind, x, cell_start, maxn, nbr=None, nnbr=None, ma
 
 
 def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn, F=None,
-                   e_atom=None, ev=None, want_energy=True, ws=None):
-    """Forces (and per-atom energy / [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] when wanted)."""
+                   e_atom=None, ev=None, want_energy=True, ws=None, atom_energy=True):
+    """Forces (and per-atom energy / [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] when wanted).
+    atom_energy=False with want_energy: E and W only (no per-atom energies are made
+    unless e_atom is given)."""
     n = x.shape[0]
     dev = x.device
     ntypes = _ntypes(eps)
@@ -137,7 +139,7 @@ def compute_forces(L, precision, kind, rc, eps, sigma, x, types, nbr, nnbr, maxn
     if F is None:
         F = torch.empty_like(x)
     if want_energy:
-        if e_atom is None:
+        if e_atom is None and atom_energy:
             e_atom = torch.empty(n, dtype=torch.float64, device=dev)
         if ev is None:
             ev = torch.empty(7, dtype=torch.float64, device=dev)

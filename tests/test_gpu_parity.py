@@ -454,6 +454,27 @@ def test_forces_without_energy_outputs(dev, oracle_forces_cache):
     assert max_rel_vec(ops.scatter_rows(ids, F).cpu().numpy(), Fo) <= FP64_TOL
 
 
+@pytest.mark.parametrize("kind", ["full", "half"])
+def test_energy_and_virial_without_atom_energies(dev, orc, oracle_forces_cache, kind):
+    """E and W with no per-atom energy array (e_atom NULL): the half list then takes its
+    three-accumulator kernel.  Forces, E and W against the oracle at the FP64 bar, on a
+    32,000-atom liquid (the half list's 128-atom, eight-lane shape)."""
+    import torch
+    from paper_2109_09056_amd import ops
+    x, L, ty, eps, sig, (Fo, eo, Wo, _) = oracle_forces_cache("lj32k")
+    k = ops.FULL if kind == "full" else ops.HALF
+    nl, ids, xs = gpu_lists(dev, x, L, 2.8, k)
+    one = T([1.0], dev, torch.float64)
+    tz = torch.zeros(x.shape[0], dtype=torch.int32, device=dev)
+    F, e, ev = ops.compute_forces(L, ops.FP64, k, 2.5, one, one, xs, tz, nl.nbr, nl.nnbr,
+                                  nl.maxn, atom_energy=False)
+    assert e is None
+    assert max_rel_vec(ops.scatter_rows(ids, F).cpu().numpy(), Fo) <= FP64_TOL
+    ev = ev.cpu().numpy()
+    assert abs(ev[0] - eo.sum()) <= FP64_TOL * abs(eo.sum())
+    assert np.abs(ev[1:] - Wo).max() <= FP64_TOL * np.abs(Wo[:3]).max()
+
+
 def test_forces_empty(dev):
     import torch
     from paper_2109_09056_amd import ops
